@@ -1,0 +1,235 @@
+"""Dual problem, its solution and what is read off it (Sections 4 and 6).
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+Notation: m is the (even) tensor order, p = m/(m-1) the primal exponent and
+lambda = 1/gamma the regularisation (the text weights the loss by gamma).
+
+  primal (eq. tensor_primal, divided by gamma):
+      P(w) = 1/(2 lambda) ||X w - y||^2 + (1/p) ||w||_p^p
+  dual (eq. dual_tensor_kernel with 1/(2 gamma) = lambda/2):
+      D(alpha) = (1/m) <K, alpha^{(x)m}> + (lambda/2) ||alpha||^2 - <y, alpha>
+  gradient      grad D = g + lambda alpha - y,   g = K . alpha^{m-1}
+  Hessian       J(alpha) + lambda I,   J = dg/dalpha = (m-1) K x_3 alpha .. x_m alpha
+  representer   w = J_q(X^T alpha) = (X^T alpha)^{m-1}   (eq. tensor_representer, q = m even)
+
+The solver is damped Newton with Armijo backtracking and a Cholesky solve of
+the n x n Newton system.  Because D is lambda-strongly convex its minimiser is
+unique, so any correct solver must reach the same alpha*.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import Callable, Optional
+
+import numpy as np
+import scipy.linalg as sla
+
+from . import tensor as T
+
+
+@dataclass
+class SolveInfo:
+    iterations: int
+    grad_norm: float
+    converged: bool
+    objective: float
+
+
+def dual_objective(g, alpha, y, lam: float, m: int) -> float:
+    """D(alpha) from g = K.alpha^{m-1}; uses <K, alpha^{(x)m}> = alpha^T g."""
+    return float(alpha @ g) / m + 0.5 * lam * float(alpha @ alpha) - float(y @ alpha)
+
+
+def dual_grad(g, alpha, y, lam: float) -> np.ndarray:
+    return g + lam * alpha - y
+
+
+def solve_dual_newton(contract: Callable, jacobian: Callable, y, lam: float, m: int,
+                      alpha0: Optional[np.ndarray] = None, rtol: float = 1e-14,
+                      max_iter: int = 500) -> tuple:
+    """Damped Newton on D.  Stops when ||grad D|| <= rtol * (||y|| + ||g|| + lam ||alpha||)
+    or when the gradient norm stops decreasing (the rounding floor)."""
+    y = np.asarray(y, dtype=np.float64)
+    n = y.size
+    a = np.zeros(n) if alpha0 is None else np.array(alpha0, dtype=np.float64)
+    g = contract(a)
+    f = dual_objective(g, a, y, lam, m)
+    gr = dual_grad(g, a, y, lam)
+    best = (np.linalg.norm(gr), a.copy())
+    stall = 0
+    it = 0
+    converged = False
+    for it in range(1, max_iter + 1):
+        gn = np.linalg.norm(gr)
+        scale = np.linalg.norm(y) + np.linalg.norm(g) + lam * np.linalg.norm(a)
+        if gn <= rtol * scale:
+            converged = True
+            it -= 1
+            break
+        H = jacobian(a) + lam * np.eye(n)
+        step = -sla.cho_solve(sla.cho_factor(H, lower=True), gr)
+        slope = float(gr @ step)
+        t = 1.0
+        while True:
+            a_new = a + t * step
+            g_new = contract(a_new)
+            f_new = dual_objective(g_new, a_new, y, lam, m)
+            if f_new <= f + 1e-4 * t * slope or t < 1e-12:
+                break
+            t *= 0.5
+        a, g, f = a_new, g_new, f_new
+        gr = dual_grad(g, a, y, lam)
+        gn_new = np.linalg.norm(gr)
+        if gn_new < best[0]:
+            best = (gn_new, a.copy())
+        # rounding floor: near the solution, Newton steps that no longer halve
+        # the gradient norm
+        if gn_new > 0.5 * gn and gn < 1e-8 * scale:
+            stall += 1
+            if stall >= 3:
+                converged = True
+                break
+        else:
+            stall = 0
+    gn, a = best
+    g = contract(a)
+    return a, SolveInfo(it, float(np.linalg.norm(dual_grad(g, a, y, lam))), converged,
+                        dual_objective(g, a, y, lam, m))
+
+
+def linear_callbacks(X, m: int):
+    """Contraction and Jacobian of the linear tensor kernel in closed form."""
+    return (lambda a: T.contract_closed(X, a, m)), (lambda a: T.jacobian_closed(X, a, m))
+
+
+def packed_callbacks(K, n: int, m: int):
+    """Contraction and Jacobian read from the packed array (any tensor kernel)."""
+    return (lambda a: T.contract_packed(K, n, m, a)), (lambda a: T.jacobian_packed(K, n, m, a))
+
+
+def solve_linear(X, y, lam: float, m: int, **kw):
+    c, j = linear_callbacks(X, m)
+    return solve_dual_newton(c, j, y, lam, m, **kw)
+
+
+def solve_path(X, y, lambdas, m: int, **kw):
+    """Independent solves along a lambda path, warm-started in increasing
+    lambda order (the minimiser of each is unique, so warm starts only change
+    the iteration count)."""
+    lambdas = np.asarray(lambdas, dtype=np.float64)
+    order = np.argsort(lambdas)
+    out = np.zeros((lambdas.size, np.asarray(y).size))
+    infos = [None] * lambdas.size
+    a0 = None
+    for k in order:
+        a, info = solve_linear(X, y, float(lambdas[k]), m, alpha0=a0, **kw)
+        out[k] = a
+        infos[k] = info
+        a0 = a
+    return out, infos
+
+
+def primal_from_dual(X, alpha, m: int) -> np.ndarray:
+    """w = J_q(X^T alpha) = (X^T alpha)^{m-1} (eq. tensor_representer, q = m even)."""
+    return (np.asarray(X, dtype=np.float64).T @ np.asarray(alpha, dtype=np.float64)) ** (m - 1)
+
+
+def primal_objective(X, y, w, lam: float, m: int) -> float:
+    p = m / (m - 1.0)
+    r = np.asarray(X) @ w - y
+    return float(r @ r) / (2.0 * lam) + float(np.sum(np.abs(w) ** p)) / p
+
+
+def duality_gap(X, y, alpha, lam: float, m: int) -> float:
+    """P(w(alpha)) + D(alpha) with w(alpha) from the representer."""
+    w = primal_from_dual(X, alpha, m)
+    g = T.contract_closed(X, alpha, m)
+    return primal_objective(X, y, w, lam, m) + dual_objective(g, alpha, y, lam, m)
+
+
+def support_threshold(w) -> tuple:
+    """Section 6.3: features whose weight magnitude exceeds twice the standard
+    deviation of the weights (population std, strict inequality)."""
+    w = np.asarray(w, dtype=np.float64)
+    tau = 2.0 * float(np.std(w))
+    return np.abs(w) > tau, tau
+
+
+def f1_score(mask, true_support) -> float:
+    pred = set(np.flatnonzero(mask).tolist())
+    true = set(np.asarray(true_support).tolist())
+    tp = len(pred & true)
+    if tp == 0:
+        return 0.0
+    prec = tp / len(pred)
+    rec = tp / len(true)
+    return 2 * prec * rec / (prec + rec)
+
+
+def predict_linear(w, Xq) -> np.ndarray:
+    """<w, x> for every query row (eq. tensor_1 left-hand side)."""
+    return np.asarray(Xq, dtype=np.float64) @ w
+
+
+def predict_kernel(X, alpha, Xq, m: int, kernel: str = "linear", kparam: float = 0.0) -> np.ndarray:
+    """General tensor kernel prediction (Section 4, general feature map):
+    f(x) = sum_{i_1..i_{m-1}} k(x_{i_1}, .., x_{i_{m-1}}, x) alpha_{i_1} .. alpha_{i_{m-1}},
+    summed over sorted (m-1)-tuples times their number of orderings.  Python
+    loops: small n only."""
+    from itertools import combinations_with_replacement
+    from math import factorial
+    from collections import Counter
+    X = np.asarray(X, dtype=np.float64)
+    Xq = np.asarray(Xq, dtype=np.float64)
+    n = X.shape[0]
+    out = np.zeros(Xq.shape[0])
+    Z = np.vstack([X, Xq])
+    for t in combinations_with_replacement(range(n), m - 1):
+        cnt = Counter(t)
+        mult = factorial(m - 1)
+        for c in cnt.values():
+            mult //= factorial(c)
+        coef = mult * float(np.prod(np.asarray(alpha)[list(t)]))
+        for q in range(Xq.shape[0]):
+            out[q] += coef * T.kernel_entry(Z, list(t) + [n + q], kernel, kparam)
+    return out
+
+
+def mse(f, y) -> float:
+    """MSE of Section 6.1: mean of squared residuals."""
+    r = np.asarray(f) - np.asarray(y)
+    return float(r @ r) / r.size
+
+
+def krr_closed_form(X, y, lam: float) -> np.ndarray:
+    """Kernel ridge regression (m = 2): the dual eq. classic_dual with
+    1/gamma = lambda is minimised by alpha = (X X^T + lambda I)^{-1} y."""
+    X = np.asarray(X, dtype=np.float64)
+    return np.linalg.solve(X @ X.T + lam * np.eye(X.shape[0]), y)
+
+
+def dalpha_dlambda(jac, alpha, lam: float) -> np.ndarray:
+    """Differentiating grad D(alpha*(lambda)) = 0 in lambda: (J + lambda I) dalpha/dlambda = -alpha*."""
+    H = jac + lam * np.eye(alpha.size)
+    return -np.linalg.solve(H, alpha)
+
+
+def val_mse_linear(X, alpha, m: int, X_val, y_val) -> float:
+    return mse(predict_linear(primal_from_dual(X, alpha, m), X_val), y_val)
+
+
+def grad_alpha_val_mse(X, alpha, m: int, X_val, y_val) -> np.ndarray:
+    """d MSE_val / d alpha = (2/N) (m-1) X diag(u^{m-2}) X_val^T r, u = X^T alpha."""
+    X = np.asarray(X, dtype=np.float64)
+    u = X.T @ alpha
+    r = X_val @ (u ** (m - 1)) - y_val
+    return (2.0 / y_val.size) * (m - 1) * (X @ ((u ** (m - 2)) * (X_val.T @ r)))
+
+
+def dmse_dlambda_linear(X, alpha, lam: float, m: int, X_val, y_val) -> float:
+    """dMSE_val/dlambda = grad_alpha MSE . dalpha*/dlambda = -z^T alpha* with
+    (J + lambda I) z = grad_alpha MSE (J symmetric)."""
+    H = T.jacobian_closed(X, alpha, m) + lam * np.eye(alpha.size)
+    z = np.linalg.solve(H, grad_alpha_val_mse(X, alpha, m, X_val, y_val))
+    return -float(z @ alpha)

@@ -1,0 +1,204 @@
+"""Pins for the oracle's dual solve, primal recovery, prediction, support
+selection and model-selection derivatives (Sections 3, 4, 6)."""
+import numpy as np
+import pytest
+from scipy.optimize import minimize
+
+from oracle import dual as D
+from oracle import precision as P
+from oracle import tensor as T
+from synth import make_workload, random_alpha
+
+
+def _small(seed=0, n=24, d=10, s=3, sigma=0.05):
+    from synth import planted_regression
+    rng = np.random.default_rng(seed)
+    X, y, w, sup = planted_regression(rng, n, d, s, sigma)
+    return X, y, w, sup
+
+
+def test_duality_maps_inverse_and_conjugate_identity():
+    """J_p o J_q = Id (Section 4) and eq. tensor_sub_jq:
+    u^T J_q(u) - (1/p)||J_q(u)||_p^p = (1/q)||u||_q^q."""
+    rng = np.random.default_rng(0)
+    for q in (2, 4, 6, 8):
+        p = q / (q - 1.0)
+        u = rng.standard_normal(50)
+        Jq = np.sign(u) * np.abs(u) ** (q - 1)
+        Jp = np.sign(Jq) * np.abs(Jq) ** (p - 1)
+        np.testing.assert_allclose(Jp, u, rtol=1e-12)
+        # q even: J_q(u) = u^{q-1}
+        np.testing.assert_allclose(Jq, u ** (q - 1), rtol=1e-14)
+        lhs = u @ Jq - np.sum(np.abs(Jq) ** p) / p
+        assert lhs == pytest.approx(np.sum(np.abs(u) ** q) / q, rel=1e-12)
+
+
+def test_order2_is_kernel_ridge_regression():
+    """m = 2: the dual is the kernel ridge dual (eq. classic_dual), whose
+    minimiser is (X X^T + lambda I)^{-1} y (LAPACK solve)."""
+    X, y, _, _ = _small(1)
+    for lam in (1e-3, 1e-1, 1.0):
+        ref = D.krr_closed_form(X, y, lam)
+        H = X @ X.T + lam * np.eye(X.shape[0])
+        tol = 100 * np.linalg.cond(H) * 2.0 ** -53      # both solves are backward stable
+        a, info = D.solve_linear(X, y, lam, 2)
+        assert np.linalg.norm(a - ref) <= tol * np.linalg.norm(ref)
+        K = T.build_packed(X, 2)
+        c, j = D.packed_callbacks(K, X.shape[0], 2)
+        a2, _ = D.solve_dual_newton(c, j, y, lam, 2)
+        assert np.linalg.norm(a2 - ref) <= tol * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("m", [4, 6])
+def test_gap_identity_at_arbitrary_alpha(m):
+    """P(w(alpha)) + D(alpha) = ||grad D(alpha)||^2 / (2 lambda) for the linear kernel."""
+    X, y, _, _ = _small(2)
+    for s in range(5):
+        a = 0.3 * random_alpha(X.shape[0], 40 + s)
+        lam = 10.0 ** (-s)
+        gap = D.duality_gap(X, y, a, lam, m)
+        gr = D.dual_grad(T.contract_closed(X, a, m), a, y, lam)
+        assert gap == pytest.approx(gr @ gr / (2 * lam), rel=1e-9)
+        assert gap >= 0
+
+
+@pytest.mark.parametrize("m,lam", [(4, 1e-2), (4, 1.0), (6, 1e-2), (4, 1e-4)])
+def test_optimality_conditions_and_strong_duality(m, lam):
+    X, y, _, _ = _small(3)
+    a, info = D.solve_linear(X, y, lam, m)
+    assert info.converged
+    w = D.primal_from_dual(X, a, m)
+    p = m / (m - 1.0)
+    # eq. jp_4 (gamma^{-1} = lambda): X^T (X w - y) + lambda J_p(w) = 0
+    # both residuals equal -X^T grad D and -grad D in exact arithmetic, so they
+    # are bounded by the dual gradient norm the solve reached (plus rounding)
+    floor = info.grad_norm + 1e-13 * (np.linalg.norm(y) + lam * np.linalg.norm(a))
+    assert info.grad_norm <= 1e-6 * np.linalg.norm(y)
+    r = X.T @ (X @ w - y) + lam * np.sign(w) * np.abs(w) ** (p - 1)
+    assert np.linalg.norm(r) <= 4 * np.linalg.norm(X, 2) * floor
+    # eq. tensor_sub_r: X w = y - lambda alpha
+    assert np.linalg.norm(X @ w - (y - lam * a)) <= 4 * floor
+    # strong duality (Section 4): min P = -min D
+    Pw = D.primal_objective(X, y, w, lam, m)
+    assert Pw == pytest.approx(-info.objective, rel=1e-9, abs=1e-10)
+
+
+def test_independent_primal_solve_matches():
+    """Minimising the d-dimensional primal directly (L-BFGS, SciPy) reaches
+    the w recovered from the dual through the representer."""
+    X, y, _, _ = _small(4, n=30, d=6)
+    m, lam = 4, 0.05
+    p = m / (m - 1.0)
+    a, _ = D.solve_linear(X, y, lam, m)
+    w_dual = D.primal_from_dual(X, a, m)
+
+    def f(w):
+        r = X @ w - y
+        val = r @ r / (2 * lam) + np.sum(np.abs(w) ** p) / p
+        grad = X.T @ r / lam + np.sign(w) * np.abs(w) ** (p - 1)
+        return val, grad
+    res = minimize(f, np.zeros(X.shape[1]), jac=True, method="L-BFGS-B",
+                   options={"maxiter": 20000, "gtol": 1e-12, "ftol": 1e-15})
+    np.testing.assert_allclose(res.x, w_dual, rtol=2e-4, atol=2e-5)
+
+
+def test_packed_solve_matches_closed_form_solve():
+    X, y, _, _ = _small(5, n=12, d=5)
+    for m in (4, 6):
+        K = T.build_packed(X, m)
+        c, j = D.packed_callbacks(K, X.shape[0], m)
+        a_p, ip = D.solve_dual_newton(c, j, y, 1e-2, m)
+        a_c, ic = D.solve_linear(X, y, 1e-2, m)
+        # strong convexity: |a_p - a*| <= |grad D(a_p)|/lambda, where the packed
+        # gradient carries its own rounding (bounded by u * sum|terms| * count)
+        E = T.abs_bound_closed(X, a_p, m)
+        slack = np.linalg.norm(E) * 2.0 ** -53 * T.packed_count(X.shape[0], m)
+        assert np.linalg.norm(a_p - a_c) <= (ip.grad_norm + ic.grad_norm + slack) / 1e-2
+        w_p, w_c = D.primal_from_dual(X, a_p, m), D.primal_from_dual(X, a_c, m)
+        np.testing.assert_allclose(w_p, w_c, rtol=1e-6, atol=1e-8 * np.abs(w_c).max())
+
+
+def test_planted_support_recovery():
+    """Section 6.3 thresholding recovers the planted support of the synthetic
+    data model (Section 5.4) on the order-4 workloads."""
+    wl = make_workload("c2_n256_m4")
+    a, _ = D.solve_linear(wl.X, wl.y, wl.lam, wl.m)
+    mask, tau = D.support_threshold(D.primal_from_dual(wl.X, a, wl.m))
+    assert D.f1_score(mask, wl.support) == 1.0
+    wl = make_workload("c1_n64_m4")
+    a, _ = D.solve_linear(wl.X, wl.y, wl.lam, wl.m)
+    mask, _ = D.support_threshold(D.primal_from_dual(wl.X, a, wl.m))
+    assert D.f1_score(mask, wl.support) >= 0.8
+
+
+def test_support_threshold_rule():
+    w = np.array([0.0, 1.0, -3.0, 0.5, 0.0, 0.0, 0.0, 0.0])
+    mask, tau = D.support_threshold(w)
+    assert tau == pytest.approx(2 * np.sqrt(np.mean((w - w.mean()) ** 2)))
+    assert np.flatnonzero(mask).tolist() == [2]
+    assert D.f1_score(mask, [2]) == 1.0
+    assert D.f1_score(mask, [1, 2]) == pytest.approx(2 * 1 * 0.5 / 1.5)
+
+
+def test_prediction_general_equals_primal_linear():
+    """eq. tensor_1: sum_j (sum_i alpha_i x_ij)^{m-1} x_j equals the multilinear
+    kernel expansion over (m-1)-tuples of training points."""
+    X, y, _, _ = _small(6, n=6, d=4)
+    Xq = np.random.default_rng(9).standard_normal((3, 4))
+    for m in (2, 4):
+        a = random_alpha(6, 11 + m)
+        f_k = D.predict_kernel(X, a, Xq, m)
+        f_w = D.predict_linear(D.primal_from_dual(X, a, m), Xq)
+        np.testing.assert_allclose(f_k, f_w, rtol=1e-12)
+
+
+def test_mse_definition():
+    assert D.mse([1.0, 2.0, 4.0], [1.0, 1.0, 1.0]) == pytest.approx((0 + 1 + 9) / 3)
+
+
+@pytest.mark.parametrize("m", [4, 6])
+def test_dalpha_dlambda_and_dmse_against_finite_differences(m):
+    X, y, _, _ = _small(7, n=20, d=8)
+    Xv, yv, _, _ = _small(8, n=50, d=8)
+    lam, h = 0.05, 1e-6
+    a, _ = D.solve_linear(X, y, lam, m)
+    ap, _ = D.solve_linear(X, y, lam + h, m, alpha0=a)
+    am, _ = D.solve_linear(X, y, lam - h, m, alpha0=a)
+    da = D.dalpha_dlambda(T.jacobian_closed(X, a, m), a, lam)
+    np.testing.assert_allclose(da, (ap - am) / (2 * h), rtol=1e-5, atol=1e-6 * np.abs(da).max())
+    dm = D.dmse_dlambda_linear(X, a, lam, m, Xv, yv)
+    fd = (D.val_mse_linear(X, ap, m, Xv, yv) - D.val_mse_linear(X, am, m, Xv, yv)) / (2 * h)
+    assert dm == pytest.approx(fd, rel=1e-5, abs=1e-9)
+
+
+def test_lambda_path_warm_starts_do_not_change_answers():
+    X, y, _, _ = _small(9, n=16, d=6)
+    lams = np.array([1.0, 1e-2, 1e-1])
+    path, infos = D.solve_path(X, y, lams, 4)
+    for k, lam in enumerate(lams):
+        a, _ = D.solve_linear(X, y, lam, 4)
+        np.testing.assert_allclose(path[k], a, rtol=1e-9, atol=1e-12)
+
+
+def test_bf16_rounding_pins():
+    """Round-to-nearest-even to 8 significant bits, checked on exact cases."""
+    r = P.round_bf16_scalar
+    assert r(1.0) == 1.0
+    assert r(1.0 + 2 ** -8) == 1.0                 # tie -> even (1.0000000)
+    assert r(1.0 + 3 * 2 ** -8) == 1.0 + 2 ** -6   # tie -> even (1.0000010)
+    assert r(1.0 + 2 ** -8 + 2 ** -30) == 1.0 + 2 ** -7
+    assert r(-(1.0 + 2 ** -7)) == -(1.0 + 2 ** -7)
+    assert r(3.0 * 2 ** 100) == 3.0 * 2 ** 100
+    assert r(2.0 ** 128) == np.inf
+    assert r((2 - 2 ** -8) * 2.0 ** 127) == np.inf          # rounds up past the largest
+    assert r((2 - 2 ** -7) * 2.0 ** 127) == (2 - 2 ** -7) * 2.0 ** 127
+    assert r(2.0 ** -133) == 2.0 ** -133                  # smallest subnormal
+    assert r(2.0 ** -134) == 0.0                          # tie to even zero
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal(2000) * 10.0 ** rng.integers(-5, 5, 2000)
+    y = P.round_bf16(x)
+    # result has 8 significant bits and is within half a unit in the last place
+    f, e = np.frexp(y)
+    assert np.all(f * 256 == np.round(f * 256))
+    assert np.all(np.abs(y - x) <= 2.0 ** (e - 9) + 0.0)
+    np.testing.assert_array_equal(P.round_fp32(x), x.astype(np.float32).astype(np.float64))
