@@ -1,0 +1,12 @@
+"""MI355X-native packed tensor-kernel regression (hot path of arXiv 2003.10482).
+
+The compute path is the HIP library ``libtk.so`` (C ABI in ``include/tk.h``);
+this package only marshals torch tensors to it.  Importing the package does not
+load the library; the first call does, and raises if it is missing.
+"""
+from .api import (  # noqa: F401
+    ACC_AUTO, ACC_COMPENSATED, ACC_F32, ACC_F64, BF16, EXP, F32, F64, LINEAR, POLY,
+    PackedTensor, TkContract, build_packed_tensor, contract, contract_autograd, contract_dense,
+    contract_workspace, dmse_dlambda, gather_rows, hvp, max_points, packed_count, predict,
+    primal_weights, solve_dual, solve_workspace, support,
+)

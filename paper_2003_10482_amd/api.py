@@ -1,0 +1,252 @@
+"""Thin torch-facing binding of the C ABI (``include/tk.h``).
+
+Every function only checks shapes, allocates outputs and workspaces with torch
+on the current HIP device and forwards raw pointers plus the current stream to
+``libtk.so``.  All arithmetic runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib
+
+F64, F32, BF16 = 0, 1, 2
+LINEAR, POLY, EXP = 0, 1, 2
+ACC_AUTO, ACC_COMPENSATED, ACC_F64, ACC_F32 = 0, 1, 2, 3
+
+_DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, F64: F64, F32: F32, BF16: BF16}
+_TORCH_STORAGE = {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16}
+_KERNELS = {"linear": LINEAR, "poly": POLY, "exp": EXP, LINEAR: LINEAR, POLY: POLY, EXP: EXP}
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _dev_f64(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != torch.float64:
+        raise ValueError(f"{name} must be float64")
+    return t.contiguous()
+
+
+def packed_count(n: int, m: int) -> int:
+    out = ctypes.c_int64()
+    _lib.check(_lib.load().tk_packed_count(n, m, ctypes.byref(out)))
+    return out.value
+
+
+def max_points() -> int:
+    return int(_lib.load().tk_max_points())
+
+
+class PackedTensor:
+    """Device buffer of a packed symmetric tensor plus its shape metadata."""
+
+    def __init__(self, data: torch.Tensor, n: int, m: int, dtype: int):
+        self.data, self.n, self.m, self.dtype = data, n, m, dtype
+
+    @property
+    def count(self) -> int:
+        return packed_count(self.n, self.m)
+
+    @property
+    def nbytes(self) -> int:
+        return self.data.numel() * self.data.element_size()
+
+
+def build_packed_tensor(X: torch.Tensor, m: int, kernel="linear", kparam: float = 0.0,
+                        dtype="f64") -> PackedTensor:
+    X = _dev_f64(X, "X")
+    n, d = X.shape
+    dt = _DTYPES[dtype]
+    K = torch.empty(packed_count(n, m), dtype=_TORCH_STORAGE[dt], device=X.device)
+    _lib.check(_lib.load().tk_build_packed_tensor(_ptr(X), n, d, m, _KERNELS[kernel], float(kparam),
+                                                  dt, _ptr(K), _stream()))
+    return PackedTensor(K, n, m, dt)
+
+
+def contract_workspace(n: int, m: int, B: int, dtype) -> int:
+    out = ctypes.c_size_t()
+    _lib.check(_lib.load().tk_contract_workspace(n, m, B, _DTYPES[dtype], ctypes.byref(out)))
+    return out.value
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+
+
+def contract(K: PackedTensor, alpha: torch.Tensor, acc: int = ACC_AUTO,
+             work: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """g = K . alpha^{m-1}; alpha [n] or [B, n] float64 -> same shape."""
+    alpha = _dev_f64(alpha, "alpha")
+    a2 = alpha.reshape(-1, K.n)
+    B = a2.shape[0]
+    g = torch.empty_like(a2) if out is None else out
+    if work is None:
+        work = _workspace(contract_workspace(K.n, K.m, B, K.dtype), alpha.device)
+    _lib.check(_lib.load().tk_contract(_ptr(K.data), K.dtype, K.n, K.m, _ptr(a2), B, _ptr(g), acc,
+                                       _ptr(work), work.numel(), _stream()))
+    return g.reshape(alpha.shape)
+
+
+def hvp(K: PackedTensor, alpha: torch.Tensor, v: torch.Tensor, with_g: bool = False,
+        work: Optional[torch.Tensor] = None):
+    """h = (m-1) K x_2 v x_3 alpha .. x_m alpha (and g when with_g)."""
+    alpha = _dev_f64(alpha, "alpha")
+    v = _dev_f64(v, "v")
+    a2 = alpha.reshape(-1, K.n)
+    v2 = v.reshape(-1, K.n)
+    if a2.shape != v2.shape:
+        raise ValueError("alpha and v shapes differ")
+    B = a2.shape[0]
+    h = torch.empty_like(a2)
+    g = torch.empty_like(a2) if with_g else None
+    if work is None:
+        work = _workspace(contract_workspace(K.n, K.m, B, K.dtype), alpha.device)
+    _lib.check(_lib.load().tk_hvp(_ptr(K.data), K.dtype, K.n, K.m, _ptr(a2), _ptr(v2), B, _ptr(h), _ptr(g),
+                                  _ptr(work), work.numel(), _stream()))
+    if with_g:
+        return h.reshape(alpha.shape), g.reshape(alpha.shape)
+    return h.reshape(alpha.shape)
+
+
+def solve_workspace(n: int, m: int, B: int, dtype) -> int:
+    out = ctypes.c_size_t()
+    _lib.check(_lib.load().tk_solve_workspace(n, m, B, _DTYPES[dtype], ctypes.byref(out)))
+    return out.value
+
+
+def solve_dual(K: PackedTensor, y: torch.Tensor, lambdas: Sequence[float], tol: float = 1e-11,
+               max_newton: int = 100, max_cg: int = 2000, fixed_iters: int = 0,
+               alpha0: Optional[torch.Tensor] = None, polish: Optional[PackedTensor] = None,
+               verbose: bool = False, raise_on_noconv: bool = False):
+    """Dual solve for every lambda (one shared pass over K per step).  Returns
+    (alpha [B, n], list of info dicts)."""
+    y = _dev_f64(y, "y")
+    lams = [float(x) for x in lambdas]
+    B = len(lams)
+    opts = _lib.SolveOpts()
+    _lib.load().tk_solve_opts_default(ctypes.byref(opts))
+    opts.tol = tol
+    opts.max_newton = max_newton
+    opts.max_cg = max_cg
+    opts.fixed_iters = fixed_iters
+    opts.verbose = int(verbose)
+    if polish is not None:
+        opts.polish_K = polish.data.data_ptr()
+        opts.polish_dtype = polish.dtype
+    alpha = torch.zeros(B, K.n, dtype=torch.float64, device=y.device)
+    if alpha0 is not None:
+        alpha.copy_(alpha0.reshape(B, K.n))
+        opts.warm_start = 1
+    infos = (_lib.SolveInfo * B)()
+    h_l = (ctypes.c_double * B)(*lams)
+    work = _workspace(solve_workspace(K.n, K.m, B, K.dtype), y.device)
+    rc = _lib.load().tk_solve_dual(_ptr(K.data), K.dtype, K.n, K.m, _ptr(y), h_l, B, ctypes.byref(opts),
+                                   _ptr(alpha), infos, _ptr(work), work.numel(), _stream())
+    if rc != 0 and (raise_on_noconv or rc not in (-5, -6)):
+        _lib.check(rc)
+    return alpha, [infos[i].as_dict() for i in range(B)]
+
+
+def primal_weights(X: torch.Tensor, alpha: torch.Tensor, m: int) -> torch.Tensor:
+    X = _dev_f64(X, "X")
+    alpha = _dev_f64(alpha, "alpha")
+    n, d = X.shape
+    a2 = alpha.reshape(-1, n)
+    W = torch.empty(a2.shape[0], d, dtype=torch.float64, device=X.device)
+    _lib.check(_lib.load().tk_primal_weights(_ptr(X), n, d, m, _ptr(a2), a2.shape[0], _ptr(W), _stream()))
+    return W if alpha.dim() == 2 else W[0]
+
+
+def predict(W: torch.Tensor, Xq: torch.Tensor) -> torch.Tensor:
+    W = _dev_f64(W, "W")
+    Xq = _dev_f64(Xq, "Xq")
+    W2 = W.reshape(-1, W.shape[-1])
+    N, d = Xq.shape
+    f = torch.empty(W2.shape[0], N, dtype=torch.float64, device=W.device)
+    _lib.check(_lib.load().tk_predict(_ptr(W2), d, W2.shape[0], _ptr(Xq), N, _ptr(f), _stream()))
+    return f if W.dim() == 2 else f[0]
+
+
+def contract_dense(X: torch.Tensor, alpha: torch.Tensor, m: int) -> torch.Tensor:
+    X = _dev_f64(X, "X")
+    alpha = _dev_f64(alpha, "alpha")
+    n, d = X.shape
+    a2 = alpha.reshape(-1, n)
+    g = torch.empty_like(a2)
+    work = torch.empty(a2.shape[0] * d, dtype=torch.float64, device=X.device)
+    _lib.check(_lib.load().tk_contract_dense(_ptr(X), n, d, m, _ptr(a2), a2.shape[0], _ptr(g), _ptr(work),
+                                             _stream()))
+    return g.reshape(alpha.shape)
+
+
+def support(W: torch.Tensor):
+    W = _dev_f64(W, "W")
+    W2 = W.reshape(-1, W.shape[-1])
+    mask = torch.empty(W2.shape, dtype=torch.uint8, device=W.device)
+    tau = torch.empty(W2.shape[0], dtype=torch.float64, device=W.device)
+    _lib.check(_lib.load().tk_support(_ptr(W2), W2.shape[1], W2.shape[0], _ptr(mask), _ptr(tau), _stream()))
+    if W.dim() == 1:
+        return mask[0].bool(), tau[0]
+    return mask.bool(), tau
+
+
+def gather_rows(X: torch.Tensor, idx: torch.Tensor) -> torch.Tensor:
+    X = _dev_f64(X, "X")
+    if idx.dtype != torch.int64 or not idx.is_cuda:
+        raise ValueError("idx must be an int64 device tensor")
+    idx = idx.contiguous()
+    N, d = X.shape
+    out = torch.empty(idx.numel(), d, dtype=torch.float64, device=X.device)
+    _lib.check(_lib.load().tk_gather_rows(_ptr(X), N, d, _ptr(idx), idx.numel(), _ptr(out), _stream()))
+    return out
+
+
+def dmse_dlambda(K: PackedTensor, X: torch.Tensor, alpha: torch.Tensor, lam: float, X_val: torch.Tensor,
+                 y_val: torch.Tensor, cg_tol: float = 1e-12, max_cg: int = 5000):
+    """(MSE_val, dMSE_val/dlambda, z) at a dual optimum alpha (implicit differentiation)."""
+    X, alpha = _dev_f64(X, "X"), _dev_f64(alpha, "alpha")
+    X_val, y_val = _dev_f64(X_val, "X_val"), _dev_f64(y_val, "y_val")
+    n, d = X.shape
+    nval = X_val.shape[0]
+    ws = ctypes.c_size_t()
+    _lib.check(_lib.load().tk_dmse_workspace(n, K.m, d, nval, K.dtype, ctypes.byref(ws)))
+    work = _workspace(ws.value, X.device)
+    z = torch.empty(n, dtype=torch.float64, device=X.device)
+    mse = ctypes.c_double()
+    dmse = ctypes.c_double()
+    _lib.check(_lib.load().tk_dmse_dlambda(_ptr(K.data), K.dtype, n, K.m, _ptr(X), d, _ptr(alpha.reshape(-1)),
+                                           float(lam), _ptr(X_val), _ptr(y_val), nval, cg_tol, max_cg,
+                                           ctypes.byref(mse), ctypes.byref(dmse), _ptr(z), _ptr(work),
+                                           work.numel(), _stream()))
+    return mse.value, dmse.value, z
+
+
+class TkContract(torch.autograd.Function):
+    """g = K . alpha^{m-1} with its adjoint: the Jacobian (m-1) K x_3 alpha .. is
+    symmetric, so the backward product is the directional derivative kernel."""
+
+    @staticmethod
+    def forward(ctx, alpha: torch.Tensor, K: PackedTensor):
+        ctx.K = K
+        ctx.save_for_backward(alpha)
+        return contract(K, alpha.detach())
+
+    @staticmethod
+    def backward(ctx, grad_g: torch.Tensor):
+        (alpha,) = ctx.saved_tensors
+        return hvp(ctx.K, alpha.detach(), grad_g.contiguous()), None
+
+
+def contract_autograd(K: PackedTensor, alpha: torch.Tensor) -> torch.Tensor:
+    return TkContract.apply(alpha, K)

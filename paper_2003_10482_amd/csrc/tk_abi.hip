@@ -1,0 +1,762 @@
+// C ABI of the packed tensor-kernel library: argument checks, workspace
+// planning, the pass sequence of the contraction, and the host-driven loops of
+// the dual solve and of the model-selection derivative.
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <vector>
+
+#include "tk_common.hpp"
+#include "tk_contract.hpp"
+#include "tk_dense.hpp"
+#include "tk_vec.hpp"
+
+namespace tk {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int check_nm(int64_t n, int m)
+{
+    if (n < 1) return fail(TK_EINVAL, "n must be >= 1 (got %lld)", (long long)n);
+    if (m < 2 || (m & 1)) return fail(TK_EINVAL, "tensor order m must be even and >= 2 (got %d)", m);
+    if (m > kMaxOrder) return fail(TK_EUNSUPPORTED, "tensor order m = %d above the compiled maximum %d", m, kMaxOrder);
+    if (n > kMaxPoints) return fail(TK_EUNSUPPORTED, "n = %lld above the compiled maximum %d", (long long)n, kMaxPoints);
+    if (checked_binom(n + m - 1, m) < 0) return fail(TK_EOVERFLOW, "C(n+m-1, m) overflows int64");
+    return TK_OK;
+}
+
+int check_dtype(int dtype)
+{
+    if (dtype != TK_F64 && dtype != TK_F32 && dtype != TK_BF16) return fail(TK_EINVAL, "unknown dtype %d", dtype);
+    return TK_OK;
+}
+
+// Layout of the contraction workspace for (n, m, B, mode, tangents).
+struct PassPlan {
+    int q;
+    int64_t count, units;
+    int groups;
+    size_t s_off, s_bytes;     // order q-2 output (and its tangent right after when hv)
+    size_t p_off, p_bytes;     // partials (and tangent partials right after)
+};
+
+struct ContractPlan {
+    int npass = 0;
+    PassPlan pass[kMaxPasses];
+    size_t bytes = 0;
+};
+
+size_t inter_size(int mode) { return mode == ACC_DD ? 16 : mode == ACC_PLAIN64 ? 8 : 4; }
+
+ContractPlan make_plan(int64_t n, int m, int64_t B, int mode, bool hv)
+{
+    ContractPlan pl;
+    size_t off = 0;
+    for (int q = m; q >= 2; q -= 2) {
+        PassPlan &p = pl.pass[pl.npass++];
+        p.q = q;
+        p.count = packed_count(n, q);
+        p.units = q >= 4 ? packed_count(n, q - 2) : 1;
+        p.groups = pass_groups(p.count);
+        p.s_bytes = q >= 4 ? align256((size_t)B * p.units * inter_size(mode)) : 0;
+        p.s_off = off;
+        off += p.s_bytes * (hv ? 2 : 1);
+        p.p_bytes = align256((size_t)B * p.groups * n * 2 * sizeof(double));
+        p.p_off = off;
+        off += p.p_bytes * (hv ? 2 : 1);
+    }
+    pl.bytes = off;
+    return pl;
+}
+
+int mode_for(int dtype, int acc, bool hv, int *mode)
+{
+    if (dtype == TK_F64) {
+        if (hv) { *mode = ACC_PLAIN64; return TK_OK; }
+        if (acc == TK_ACC_AUTO || acc == TK_ACC_COMPENSATED) { *mode = ACC_DD; return TK_OK; }
+        if (acc == TK_ACC_F64) { *mode = ACC_PLAIN64; return TK_OK; }
+        return fail(TK_EINVAL, "accumulation %d not available for FP64 storage", acc);
+    }
+    if (acc == TK_ACC_AUTO || acc == TK_ACC_F32) { *mode = ACC_PLAIN32; return TK_OK; }
+    return fail(TK_EINVAL, "accumulation %d not available for FP32/BF16 storage", acc);
+}
+
+// Run every pass of the contraction (and its tangent when vdir != null).
+int run_contract(const void *K, int dtype, int64_t n, int m, const double *alpha, const double *vdir,
+                 int64_t B, double *g, double *h, int mode, void *work, size_t work_bytes, hipStream_t st)
+{
+    const bool hv = vdir != nullptr;
+    const ContractPlan pl = make_plan(n, m, B, mode, hv);
+    if (work_bytes < pl.bytes || (pl.bytes && !work))
+        return fail(TK_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", work_bytes, pl.bytes);
+    unsigned char *w = reinterpret_cast<unsigned char *>(work);
+    const void *A = K;
+    const void *Ad = nullptr;
+    int in_kind = dtype == TK_F64 ? 0 : dtype == TK_F32 ? 1 : 2;
+    int64_t a_stride = 0;
+    double mu = 1.0;
+    ReduceParams rv{}, rt{};
+    for (int i = 0; i < pl.npass; ++i) {
+        const PassPlan &pp = pl.pass[i];
+        PairParams prm{};
+        prm.A = A;
+        prm.Ad = Ad;
+        prm.a_stride = a_stride;
+        prm.count = pp.count;
+        prm.units = pp.units;
+        prm.B = B;
+        prm.n = (int)n;
+        prm.mu = mu;
+        prm.alpha = alpha;
+        prm.vdir = vdir;
+        prm.S_out = pp.s_bytes ? w + pp.s_off : nullptr;
+        prm.Sd_out = (pp.s_bytes && hv) ? w + pp.s_off + pp.s_bytes : nullptr;
+        prm.part = reinterpret_cast<double *>(w + pp.p_off);
+        prm.part_d = hv ? reinterpret_cast<double *>(w + pp.p_off + pp.p_bytes) : nullptr;
+        const int hvl = hv ? (i == 0 ? 1 : 2) : 0;
+        const int bt = (i == 0 && mode == ACC_PLAIN32) ? 4 : 1;
+        hipError_t e = launch_pass(pp.q, in_kind, mode, hvl, bt, prm, pp.groups, st);
+        if (e != hipSuccess) return fail(TK_EHIP, "contraction pass q=%d failed: %s", pp.q, hipGetErrorString(e));
+        rv.part[i] = prm.part;
+        rv.groups[i] = pp.groups;
+        rt.part[i] = prm.part_d;
+        rt.groups[i] = pp.groups;
+        A = prm.S_out;
+        Ad = prm.Sd_out;
+        a_stride = pp.units;
+        in_kind = mode == ACC_DD ? 3 : mode == ACC_PLAIN64 ? 0 : 1;
+        mu *= (double)(pp.q - 1) * (double)(pp.q - 2);
+    }
+    rv.npass = rt.npass = pl.npass;
+    rv.n = rt.n = (int)n;
+    if (g) {
+        rv.out = g;
+        hipError_t e = launch_reduce(rv, B, st);
+        if (e != hipSuccess) return fail(TK_EHIP, "reduction failed: %s", hipGetErrorString(e));
+    }
+    if (hv && h) {
+        rt.out = h;
+        hipError_t e = launch_reduce(rt, B, st);
+        if (e != hipSuccess) return fail(TK_EHIP, "reduction failed: %s", hipGetErrorString(e));
+    }
+    return TK_OK;
+}
+
+size_t contract_ws(int64_t n, int m, int64_t B, int dtype)
+{
+    size_t a = make_plan(n, m, B, dtype == TK_F64 ? ACC_DD : ACC_PLAIN32, false).bytes;
+    size_t b = make_plan(n, m, B, dtype == TK_F64 ? ACC_PLAIN64 : ACC_PLAIN32, true).bytes;
+    return a > b ? a : b;
+}
+
+}  // namespace
+}  // namespace tk
+
+using namespace tk;
+
+extern "C" {
+
+const char *tk_last_error(void) { return tk::g_err; }
+
+int64_t tk_max_points(void) { return kMaxPoints; }
+
+int tk_packed_count(int64_t n, int m, int64_t *h_count)
+{
+    if (!h_count) return fail(TK_EINVAL, "null output pointer");
+    if (n < 1 || m < 1) return fail(TK_EINVAL, "n and m must be >= 1");
+    const int64_t c = checked_binom(n + m - 1, m);
+    if (c < 0) return fail(TK_EOVERFLOW, "C(n+m-1, m) overflows int64");
+    *h_count = c;
+    return TK_OK;
+}
+
+int tk_packed_bytes(int64_t n, int m, int dtype, int64_t *h_bytes)
+{
+    int64_t c;
+    int rc = tk_packed_count(n, m, &c);
+    if (rc) return rc;
+    if ((rc = check_dtype(dtype))) return rc;
+    const int64_t s = (int64_t)dtype_size(dtype);
+    if (c > INT64_MAX / s) return fail(TK_EOVERFLOW, "packed byte count overflows int64");
+    if (!h_bytes) return fail(TK_EINVAL, "null output pointer");
+    *h_bytes = c * s;
+    return TK_OK;
+}
+
+int tk_build_packed_tensor(const double *d_X, int64_t n, int64_t d, int m, int kernel, double kparam,
+                           int dtype, void *d_K, void *stream)
+{
+    int rc;
+    if ((rc = check_nm(n, m))) return rc;
+    if ((rc = check_dtype(dtype))) return rc;
+    if (d < 1 || d > INT32_MAX) return fail(TK_EINVAL, "d must be in [1, 2^31) (got %lld)", (long long)d);
+    if (!d_X || !d_K) return fail(TK_EINVAL, "null device pointer");
+    if (kernel == TK_POLY) {
+        if (!(kparam >= 1.0) || kparam != std::floor(kparam) || kparam > 64)
+            return fail(TK_EINVAL, "polynomial degree must be an integer in [1, 64]");
+    } else if (kernel != TK_LINEAR && kernel != TK_EXP) {
+        return fail(TK_EINVAL, "unknown kernel %d", kernel);
+    }
+    hipError_t e = launch_build(d_X, (int)n, (int)d, m, kernel, kparam, dtype, d_K, as_stream(stream));
+    if (e != hipSuccess) return fail(TK_EHIP, "build launch failed: %s", hipGetErrorString(e));
+    return TK_OK;
+}
+
+int tk_contract_workspace(int64_t n, int m, int64_t B, int dtype, size_t *h_bytes)
+{
+    int rc;
+    if ((rc = check_nm(n, m))) return rc;
+    if ((rc = check_dtype(dtype))) return rc;
+    if (B < 1) return fail(TK_EINVAL, "B must be >= 1");
+    if (!h_bytes) return fail(TK_EINVAL, "null output pointer");
+    *h_bytes = contract_ws(n, m, B, dtype);
+    return TK_OK;
+}
+
+int tk_contract(const void *d_K, int dtype, int64_t n, int m, const double *d_alpha, int64_t B, double *d_g,
+                int acc, void *d_work, size_t work_bytes, void *stream)
+{
+    int rc;
+    if ((rc = check_nm(n, m))) return rc;
+    if ((rc = check_dtype(dtype))) return rc;
+    if (B < 1 || B > 65535) return fail(TK_EINVAL, "B must be in [1, 65535]");
+    if (!d_K || !d_alpha || !d_g) return fail(TK_EINVAL, "null device pointer");
+    int mode;
+    if ((rc = mode_for(dtype, acc, false, &mode))) return rc;
+    return run_contract(d_K, dtype, n, m, d_alpha, nullptr, B, d_g, nullptr, mode, d_work, work_bytes,
+                        as_stream(stream));
+}
+
+int tk_hvp(const void *d_K, int dtype, int64_t n, int m, const double *d_alpha, const double *d_v, int64_t B,
+           double *d_h, double *d_g, void *d_work, size_t work_bytes, void *stream)
+{
+    int rc;
+    if ((rc = check_nm(n, m))) return rc;
+    if ((rc = check_dtype(dtype))) return rc;
+    if (B < 1 || B > 65535) return fail(TK_EINVAL, "B must be in [1, 65535]");
+    if (!d_K || !d_alpha || !d_v || !d_h) return fail(TK_EINVAL, "null device pointer");
+    int mode;
+    if ((rc = mode_for(dtype, TK_ACC_AUTO, true, &mode))) return rc;
+    return run_contract(d_K, dtype, n, m, d_alpha, d_v, B, d_g, d_h, mode, d_work, work_bytes, as_stream(stream));
+}
+
+void tk_solve_opts_default(tk_solve_opts *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->max_newton = 100;
+    o->max_cg = 2000;
+    o->tol = 1e-11;
+    o->polish_dtype = TK_F64;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ dual solve ----
+namespace tk {
+namespace {
+
+struct SolveBuffers {
+    double *g, *grad, *x, *r, *dv, *hd, *at, *gt, *stats;
+    unsigned char *cw;
+    size_t cw_bytes;
+};
+
+size_t solve_ws(int64_t n, int m, int64_t B, int dtype)
+{
+    const size_t vec = align256((size_t)B * n * sizeof(double));
+    size_t cw = contract_ws(n, m, B, dtype);
+    const size_t cw64 = contract_ws(n, m, B, TK_F64);   // polish passes on an FP64 tensor
+    if (cw64 > cw) cw = cw64;
+    return 8 * vec + align256((size_t)B * 8 * sizeof(double)) + cw;
+}
+
+SolveBuffers carve(void *work, int64_t n, int64_t B, size_t total)
+{
+    SolveBuffers s{};
+    const size_t vec = align256((size_t)B * n * sizeof(double));
+    unsigned char *w = reinterpret_cast<unsigned char *>(work);
+    double **v[8] = {&s.g, &s.grad, &s.x, &s.r, &s.dv, &s.hd, &s.at, &s.gt};
+    for (int i = 0; i < 8; ++i) *v[i] = reinterpret_cast<double *>(w + i * vec);
+    s.stats = reinterpret_cast<double *>(w + 8 * vec);
+    const size_t used = 8 * vec + align256((size_t)B * 8 * sizeof(double));
+    s.cw = w + used;
+    s.cw_bytes = total - used;
+    return s;
+}
+
+struct ProblemState {
+    double lam;
+    double D, gn, an, ag, aa, ya;
+    int newton, cg, status;
+    bool done;
+};
+
+// One batch (B <= kMaxCoefs) of dual solves.  Newton direction from CG on
+// (J + lambda I) p = -grad (truncated with an Eisenstat-Walker forcing term),
+// Armijo backtracking on D.  Gradients: compensated FP64 on FP64 storage,
+// otherwise FP32 accumulation; the optional polish continues on an FP64 tensor.
+int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, const double *lams, int64_t B,
+                const tk_solve_opts &o, double *alpha, tk_solve_info *info, SolveBuffers &sb, hipStream_t st)
+{
+    std::vector<ProblemState> ps(B);
+    for (int64_t b = 0; b < B; ++b) {
+        ps[b] = ProblemState{};
+        ps[b].lam = lams[b];
+    }
+    Coefs lam{}, zero{}, one{}, minus1{};
+    for (int64_t b = 0; b < B; ++b) {
+        lam.c[b] = lams[b];
+        one.c[b] = 1.0;
+        minus1.c[b] = -1.0;
+    }
+    int passes = 0;
+    std::vector<double> hst(B * 4), hd(B), hr(B);
+    const double inv_m = 1.0 / m;
+
+    auto sync_copy = [&](double *dst, const double *src, size_t cnt) -> int {
+        TK_HIP_CHECK(hipMemcpyAsync(dst, src, cnt * sizeof(double), hipMemcpyDeviceToHost, st));
+        TK_HIP_CHECK(hipStreamSynchronize(st));
+        return TK_OK;
+    };
+    // gradient pass at `a` into (gdst, graddst), statistics to the host
+    auto gradient = [&](const void *Kp, int dt, const double *a, double *gdst, double *graddst,
+                        std::vector<double> &out) -> int {
+        int mode = dt == TK_F64 ? ACC_DD : ACC_PLAIN32;
+        int rc = run_contract(Kp, dt, n, m, a, nullptr, B, gdst, nullptr, mode, sb.cw, sb.cw_bytes, st);
+        if (rc) return rc;
+        passes++;
+        TK_HIP_CHECK(vec_grad(gdst, a, y, lam, graddst, sb.stats, B, n, st));
+        return sync_copy(out.data(), sb.stats, B * 4);
+    };
+
+    const int phases = (dtype != TK_F64 && o.polish_K) ? 2 : 1;
+    int rc = TK_OK;
+    for (int phase = 0; phase < phases; ++phase) {
+        const void *Kp = phase == 0 ? K : o.polish_K;
+        const int dt = phase == 0 ? dtype : TK_F64;
+        const int hv_mode = dt == TK_F64 ? ACC_PLAIN64 : ACC_PLAIN32;
+        // reduced-precision phase followed by a polish: stop the first phase at a looser tolerance
+        const double tol = (phases == 2 && phase == 0) ? std::max(o.tol, 1e-6) : o.tol;
+        for (int64_t b = 0; b < B; ++b) {
+            ps[b].done = false;
+            ps[b].status = TK_OK;
+        }
+        if ((rc = gradient(Kp, dt, alpha, sb.g, sb.grad, hst))) return rc;
+        for (int64_t b = 0; b < B; ++b) {
+            ProblemState &s = ps[b];
+            s.ag = hst[4 * b];
+            s.aa = hst[4 * b + 1];
+            s.ya = hst[4 * b + 2];
+            s.gn = std::sqrt(hst[4 * b + 3]);
+            s.an = std::sqrt(s.aa);
+            s.D = inv_m * s.ag + 0.5 * s.lam * s.aa - s.ya;
+        }
+        const int max_newton = o.fixed_iters > 0 ? o.fixed_iters : (o.max_newton > 0 ? o.max_newton : 100);
+        double gn0[kMaxCoefs];
+        for (int64_t b = 0; b < B; ++b) gn0[b] = ps[b].gn > 0 ? ps[b].gn : 1.0;
+        for (int it = 0; it < max_newton; ++it) {
+            bool any = false;
+            for (int64_t b = 0; b < B; ++b) {
+                ProblemState &s = ps[b];
+                if (!std::isfinite(s.gn) || !std::isfinite(s.D)) {
+                    s.done = true;
+                    s.status = TK_ENAN;
+                }
+                if (!s.done && o.fixed_iters <= 0 && s.gn <= tol * s.lam * s.an && s.an > 0) s.done = true;
+                any |= !s.done;
+            }
+            if (!any) break;
+            // ---- CG on (J + lam I) x = -grad for the active problems
+            Coefs zc{}, act{};
+            for (int64_t b = 0; b < B; ++b) act.c[b] = ps[b].done ? 0.0 : 1.0;
+            TK_HIP_CHECK(vec_lin2(sb.grad, sb.grad, zero, zero, sb.x, B, n, st));         // x = 0
+            TK_HIP_CHECK(vec_lin2(sb.grad, sb.grad, minus1, zero, sb.r, B, n, st));       // r = -grad
+            TK_HIP_CHECK(vec_lin2(sb.r, sb.r, one, zero, sb.dv, B, n, st));               // d = r
+            std::vector<double> rr(B), eta(B);
+            std::vector<bool> cg_on(B);
+            for (int64_t b = 0; b < B; ++b) {
+                rr[b] = ps[b].gn * ps[b].gn;
+                const double f = std::sqrt(ps[b].gn / gn0[b]);
+                eta[b] = std::min(0.5, std::max(f, 1e-12));
+                cg_on[b] = !ps[b].done && rr[b] > 0;
+            }
+            const int max_cg = o.max_cg > 0 ? o.max_cg : 2000;
+            for (int j = 0; j < max_cg; ++j) {
+                bool anycg = false;
+                for (int64_t b = 0; b < B; ++b) anycg |= cg_on[b];
+                if (!anycg) break;
+                if ((rc = run_contract(Kp, dt, n, m, alpha, sb.dv, B, nullptr, sb.hd, hv_mode, sb.cw, sb.cw_bytes, st)))
+                    return rc;
+                passes++;
+                TK_HIP_CHECK(vec_shift_dot(sb.dv, sb.hd, lam, sb.stats, B, n, st));
+                if ((rc = sync_copy(hd.data(), sb.stats, B))) return rc;
+                Coefs a{};
+                for (int64_t b = 0; b < B; ++b) {
+                    if (!cg_on[b]) continue;
+                    if (!(hd[b] > 0) || !std::isfinite(hd[b])) {   // no positive curvature along d
+                        cg_on[b] = false;
+                        continue;
+                    }
+                    a.c[b] = rr[b] / hd[b];
+                    ps[b].cg++;
+                }
+                TK_HIP_CHECK(vec_cg_update(sb.x, sb.r, sb.dv, sb.hd, a, sb.stats, B, n, st));
+                if ((rc = sync_copy(hr.data(), sb.stats, B))) return rc;
+                Coefs beta{}, keep{};
+                for (int64_t b = 0; b < B; ++b) {
+                    keep.c[b] = 1.0;
+                    if (!cg_on[b]) continue;
+                    if (std::sqrt(hr[b]) <= eta[b] * ps[b].gn) {
+                        cg_on[b] = false;
+                        continue;
+                    }
+                    beta.c[b] = hr[b] / rr[b];
+                    rr[b] = hr[b];
+                }
+                // d = r + beta d for the problems still iterating (others unchanged: r + 0 d is not used)
+                TK_HIP_CHECK(vec_lin2(sb.r, sb.dv, keep, beta, sb.dv, B, n, st));
+            }
+            // if CG produced nothing (zero curvature at the first step), fall back to steepest descent
+            TK_HIP_CHECK(vec_dot(sb.x, sb.x, n, sb.stats, B, n, st));
+            if ((rc = sync_copy(hr.data(), sb.stats, B))) return rc;
+            {
+                Coefs c1{}, c2{};
+                for (int64_t b = 0; b < B; ++b) {
+                    c1.c[b] = 1.0;
+                    if (!ps[b].done && !(hr[b] > 0)) {
+                        c1.c[b] = 0.0;
+                        c2.c[b] = -1.0 / std::max(ps[b].lam, 1e-300);
+                    }
+                }
+                TK_HIP_CHECK(vec_lin2(sb.x, sb.grad, c1, c2, sb.x, B, n, st));
+            }
+            // slope = grad . x
+            TK_HIP_CHECK(vec_dot(sb.grad, sb.x, n, sb.stats, B, n, st));
+            std::vector<double> slope(B), t(B, 1.0);
+            if ((rc = sync_copy(slope.data(), sb.stats, B))) return rc;
+            std::vector<bool> ls(B);
+            for (int64_t b = 0; b < B; ++b) ls[b] = !ps[b].done;
+            for (int trial = 0; trial < 60; ++trial) {
+                bool anyls = false;
+                Coefs tc{};
+                for (int64_t b = 0; b < B; ++b) {
+                    anyls |= ls[b];
+                    tc.c[b] = ls[b] ? t[b] : 0.0;
+                }
+                if (!anyls) break;
+                TK_HIP_CHECK(vec_lin2(alpha, sb.x, one, tc, sb.at, B, n, st));   // at = alpha + t x
+                if ((rc = gradient(Kp, dt, sb.at, sb.gt, sb.hd, hst))) return rc;
+                Coefs acc_c{}, keep_c{};
+                bool anyacc = false;
+                for (int64_t b = 0; b < B; ++b) {
+                    keep_c.c[b] = 1.0;
+                    if (!ls[b]) continue;
+                    const double Dn = inv_m * hst[4 * b] + 0.5 * ps[b].lam * hst[4 * b + 1] - hst[4 * b + 2];
+                    const bool ok = std::isfinite(Dn) &&
+                                    (Dn <= ps[b].D + 1e-4 * t[b] * slope[b] ||
+                                     // below rounding of D: accept if the gradient norm decreased
+                                     (std::fabs(Dn - ps[b].D) <= 1e-14 * (std::fabs(ps[b].D) + 1) &&
+                                      std::sqrt(hst[4 * b + 3]) < ps[b].gn));
+                    if (ok) {
+                        ls[b] = false;
+                        acc_c.c[b] = 1.0;
+                        keep_c.c[b] = 0.0;
+                        anyacc = true;
+                        ProblemState &s = ps[b];
+                        s.ag = hst[4 * b];
+                        s.aa = hst[4 * b + 1];
+                        s.ya = hst[4 * b + 2];
+                        s.gn = std::sqrt(hst[4 * b + 3]);
+                        s.an = std::sqrt(s.aa);
+                        s.D = Dn;
+                        s.newton++;
+                    } else {
+                        t[b] *= 0.5;
+                        if (t[b] < 1e-14) {   // no decrease possible: rounding floor
+                            ls[b] = false;
+                            ps[b].done = true;
+                        }
+                    }
+                }
+                if (anyacc) {
+                    // accepted problems: alpha <- at, g <- gt, grad <- (hd holds grad of at)
+                    TK_HIP_CHECK(vec_lin2(alpha, sb.at, keep_c, acc_c, alpha, B, n, st));
+                    TK_HIP_CHECK(vec_lin2(sb.g, sb.gt, keep_c, acc_c, sb.g, B, n, st));
+                    TK_HIP_CHECK(vec_lin2(sb.grad, sb.hd, keep_c, acc_c, sb.grad, B, n, st));
+                }
+            }
+            if (o.verbose) {
+                for (int64_t b = 0; b < B; ++b)
+                    fprintf(stderr, "[tk_solve] phase %d it %d lam %.3e |grad| %.3e D %.15e |a| %.3e cg %d\n", phase, it,
+                            ps[b].lam, ps[b].gn, ps[b].D, ps[b].an, ps[b].cg);
+            }
+        }
+        for (int64_t b = 0; b < B; ++b) {
+            ProblemState &s = ps[b];
+            if (s.status == TK_OK && o.fixed_iters <= 0 && !(s.gn <= tol * s.lam * s.an)) s.status = TK_ENOCONV;
+        }
+    }
+    int overall = TK_OK;
+    for (int64_t b = 0; b < B; ++b) {
+        tk_solve_info &inf = info[b];
+        inf.newton_iters = ps[b].newton;
+        inf.cg_iters = ps[b].cg;
+        inf.passes = passes;
+        inf.grad_norm = ps[b].gn;
+        inf.objective = ps[b].D;
+        inf.alpha_norm = ps[b].an;
+        inf.status = ps[b].status;
+        if (ps[b].status != TK_OK) overall = ps[b].status;
+    }
+    return overall;
+}
+
+}  // namespace
+}  // namespace tk
+
+extern "C" {
+
+int tk_solve_workspace(int64_t n, int m, int64_t B, int dtype, size_t *h_bytes)
+{
+    int rc;
+    if ((rc = check_nm(n, m))) return rc;
+    if ((rc = check_dtype(dtype))) return rc;
+    if (B < 1) return fail(TK_EINVAL, "B must be >= 1");
+    if (!h_bytes) return fail(TK_EINVAL, "null output pointer");
+    const int64_t bb = B < kMaxCoefs ? B : kMaxCoefs;
+    *h_bytes = solve_ws(n, m, bb, dtype);
+    return TK_OK;
+}
+
+int tk_solve_dual(const void *d_K, int dtype, int64_t n, int m, const double *d_y, const double *h_lambdas,
+                  int64_t B, const tk_solve_opts *h_opts, double *d_alpha, tk_solve_info *h_info, void *d_work,
+                  size_t work_bytes, void *stream)
+{
+    int rc;
+    if ((rc = check_nm(n, m))) return rc;
+    if ((rc = check_dtype(dtype))) return rc;
+    if (B < 1) return fail(TK_EINVAL, "B must be >= 1");
+    if (!d_K || !d_y || !h_lambdas || !d_alpha || !h_info) return fail(TK_EINVAL, "null pointer");
+    tk_solve_opts o;
+    tk_solve_opts_default(&o);
+    if (h_opts) o = *h_opts;
+    if (o.polish_K && o.polish_dtype != TK_F64) return fail(TK_EINVAL, "the polish tensor must be FP64");
+    for (int64_t b = 0; b < B; ++b)
+        if (!(h_lambdas[b] > 0) || !std::isfinite(h_lambdas[b]))
+            return fail(TK_EINVAL, "lambda[%lld] must be positive and finite", (long long)b);
+    const int64_t bb = B < kMaxCoefs ? B : kMaxCoefs;
+    const size_t need = solve_ws(n, m, bb, dtype);
+    if (work_bytes < need || !d_work) return fail(TK_ENOMEM, "solve workspace of %zu bytes < %zu", work_bytes, need);
+    hipStream_t st = as_stream(stream);
+    int overall = TK_OK;
+    for (int64_t b0 = 0; b0 < B; b0 += kMaxCoefs) {
+        const int64_t nb = (B - b0) < kMaxCoefs ? (B - b0) : kMaxCoefs;
+        double *a = d_alpha + b0 * n;
+        if (!o.warm_start) TK_HIP_CHECK(hipMemsetAsync(a, 0, (size_t)nb * n * sizeof(double), st));
+        SolveBuffers sb = carve(d_work, n, nb, work_bytes);
+        rc = solve_batch(d_K, dtype, n, m, d_y, h_lambdas + b0, nb, o, a, h_info + b0, sb, st);
+        if (rc != TK_OK && rc != TK_ENOCONV && rc != TK_ENAN) return rc;
+        if (rc != TK_OK) overall = rc;
+    }
+    if (overall == TK_ENOCONV) fail(TK_ENOCONV, "at least one lambda did not reach the tolerance");
+    if (overall == TK_ENAN) fail(TK_ENAN, "non-finite values met during the solve");
+    return overall;
+}
+
+int tk_primal_weights(const double *d_X, int64_t n, int64_t d, int m, const double *d_alpha, int64_t B,
+                      double *d_W, void *stream)
+{
+    if (n < 1 || d < 1 || B < 1) return fail(TK_EINVAL, "sizes must be >= 1");
+    if (m < 2 || (m & 1)) return fail(TK_EINVAL, "m must be even and >= 2");
+    if (!d_X || !d_alpha || !d_W) return fail(TK_EINVAL, "null device pointer");
+    // W[b][j] = (sum_i alpha[b][i] X[i][j])^{m-1}
+    hipError_t e = launch_gemm(d_alpha, n, d_X, d, 1, d_W, d, B, d, n, m - 1, as_stream(stream));
+    if (e != hipSuccess) return fail(TK_EHIP, "gemm failed: %s", hipGetErrorString(e));
+    return TK_OK;
+}
+
+int tk_predict(const double *d_W, int64_t d, int64_t B, const double *d_Xq, int64_t N, double *d_f, void *stream)
+{
+    if (d < 1 || B < 1 || N < 1) return fail(TK_EINVAL, "sizes must be >= 1");
+    if (!d_W || !d_Xq || !d_f) return fail(TK_EINVAL, "null device pointer");
+    // f[b][q] = sum_j W[b][j] Xq[q][j]
+    hipError_t e = launch_gemm(d_W, d, d_Xq, 1, d, d_f, N, B, N, d, 1, as_stream(stream));
+    if (e != hipSuccess) return fail(TK_EHIP, "gemm failed: %s", hipGetErrorString(e));
+    return TK_OK;
+}
+
+int tk_contract_dense(const double *d_X, int64_t n, int64_t d, int m, const double *d_alpha, int64_t B,
+                      double *d_g, double *d_work, void *stream)
+{
+    int rc = tk_primal_weights(d_X, n, d, m, d_alpha, B, d_work, stream);
+    if (rc) return rc;
+    if (!d_g) return fail(TK_EINVAL, "null device pointer");
+    // g[b][i] = sum_j W[b][j] X[i][j]
+    hipError_t e = launch_gemm(d_work, d, d_X, 1, d, d_g, n, B, n, d, 1, as_stream(stream));
+    if (e != hipSuccess) return fail(TK_EHIP, "gemm failed: %s", hipGetErrorString(e));
+    return TK_OK;
+}
+
+int tk_support(const double *d_W, int64_t d, int64_t B, uint8_t *d_mask, double *d_tau, void *stream)
+{
+    if (d < 1 || B < 1) return fail(TK_EINVAL, "sizes must be >= 1");
+    if (!d_W || !d_mask || !d_tau) return fail(TK_EINVAL, "null device pointer");
+    hipError_t e = launch_support(d_W, d, B, d_mask, d_tau, as_stream(stream));
+    if (e != hipSuccess) return fail(TK_EHIP, "support failed: %s", hipGetErrorString(e));
+    return TK_OK;
+}
+
+int tk_gather_rows(const double *d_X, int64_t N, int64_t d, const int64_t *d_idx, int64_t l, double *d_out,
+                   void *stream)
+{
+    if (N < 1 || d < 1 || l < 1 || l > 65535) return fail(TK_EINVAL, "sizes out of range");
+    if (!d_X || !d_idx || !d_out) return fail(TK_EINVAL, "null device pointer");
+    hipStream_t st = as_stream(stream);
+    int *flag = nullptr;
+    TK_HIP_CHECK(hipMallocAsync((void **)&flag, sizeof(int), st));
+    TK_HIP_CHECK(hipMemsetAsync(flag, 0, sizeof(int), st));
+    hipError_t e = launch_gather(d_X, N, d, d_idx, l, d_out, flag, st);
+    int bad = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFreeAsync(flag, st);
+    if (e != hipSuccess) return fail(TK_EHIP, "gather failed: %s", hipGetErrorString(e));
+    if (bad) return fail(TK_EINVAL, "an index is outside [0, N)");
+    return TK_OK;
+}
+
+int tk_dmse_workspace(int64_t n, int m, int64_t d, int64_t nval, int dtype, size_t *h_bytes)
+{
+    int rc;
+    if ((rc = check_nm(n, m))) return rc;
+    if ((rc = check_dtype(dtype))) return rc;
+    if (!h_bytes) return fail(TK_EINVAL, "null output pointer");
+    const size_t vn = align256(n * sizeof(double)), vd = align256(d * sizeof(double));
+    const size_t vv = align256(nval * sizeof(double));
+    *h_bytes = 6 * vn + 4 * vd + vv + align256(64 * sizeof(double)) + contract_ws(n, m, 1, dtype);
+    return TK_OK;
+}
+
+int tk_dmse_dlambda(const void *d_K, int dtype, int64_t n, int m, const double *d_X, int64_t d,
+                    const double *d_alpha, double lambda, const double *d_Xval, const double *d_yval, int64_t nval,
+                    double cg_tol, int max_cg, double *h_mse, double *h_dmse, double *d_z, void *d_work,
+                    size_t work_bytes, void *stream)
+{
+    int rc;
+    if ((rc = check_nm(n, m))) return rc;
+    if ((rc = check_dtype(dtype))) return rc;
+    if (!(lambda > 0)) return fail(TK_EINVAL, "lambda must be positive");
+    if (d < 1 || nval < 1) return fail(TK_EINVAL, "sizes must be >= 1");
+    if (!d_K || !d_X || !d_alpha || !d_Xval || !d_yval || !h_mse || !h_dmse) return fail(TK_EINVAL, "null pointer");
+    size_t need;
+    if ((rc = tk_dmse_workspace(n, m, d, nval, dtype, &need))) return rc;
+    if (work_bytes < need || !d_work) return fail(TK_ENOMEM, "workspace of %zu bytes < %zu", work_bytes, need);
+    hipStream_t st = as_stream(stream);
+    const size_t vn = align256(n * sizeof(double)), vd = align256(d * sizeof(double));
+    const size_t vv = align256(nval * sizeof(double));
+    unsigned char *w = reinterpret_cast<unsigned char *>(d_work);
+    double *u = (double *)w;            w += vd;   // X^T alpha
+    double *wv = (double *)w;           w += vd;   // w = u^{m-1}
+    double *sv = (double *)w;           w += vd;   // X_val^T r
+    double *tv = (double *)w;           w += vd;   // u^{m-2} * s
+    double *res = (double *)w;          w += vv;   // residual on the validation set
+    double *rhs = (double *)w;          w += vn;
+    double *x = (double *)w;            w += vn;
+    double *r = (double *)w;            w += vn;
+    double *dv = (double *)w;           w += vn;
+    double *hd = (double *)w;           w += vn;
+    double *tmp = (double *)w;          w += vn;
+    double *sc = (double *)w;           w += align256(64 * sizeof(double));
+    unsigned char *cw = w;
+    const size_t cw_bytes = work_bytes - (size_t)(w - reinterpret_cast<unsigned char *>(d_work));
+    (void)tmp;
+    hipError_t e;
+#define TK_CHK(x)                                                                   \
+    do {                                                                            \
+        e = (x);                                                                    \
+        if (e != hipSuccess) return fail(TK_EHIP, "%s: %s", #x, hipGetErrorString(e)); \
+    } while (0)
+    // u = X^T alpha, w = u^{m-1}
+    TK_CHK(launch_gemm(d_alpha, n, d_X, d, 1, u, d, 1, d, n, 1, st));
+    TK_CHK(launch_gemm(d_alpha, n, d_X, d, 1, wv, d, 1, d, n, m - 1, st));
+    // res = X_val w - y_val
+    TK_CHK(launch_gemm(wv, d, d_Xval, 1, d, res, nval, 1, nval, d, 1, st));
+    TK_CHK(vec_sub(res, d_yval, res, nval, st));
+    double hs[2];
+    TK_CHK(vec_dot(res, res, 0, sc, 1, nval, st));
+    TK_CHK(hipMemcpyAsync(hs, sc, sizeof(double), hipMemcpyDeviceToHost, st));
+    TK_CHK(hipStreamSynchronize(st));
+    *h_mse = hs[0] / (double)nval;
+    // s = X_val^T res ; t = u^{m-2} s ; rhs = (2/N)(m-1) X t
+    TK_CHK(launch_gemm(res, nval, d_Xval, d, 1, sv, d, 1, d, nval, 1, st));
+    TK_CHK(vec_pow_mul(u, sv, m - 2, tv, d, st));
+    TK_CHK(launch_gemm(tv, d, d_X, 1, d, rhs, n, 1, n, d, 1, st));
+    Coefs sc2{}, zc{}, onec{}, lamc{};
+    sc2.c[0] = 2.0 * (m - 1) / (double)nval;
+    onec.c[0] = 1.0;
+    lamc.c[0] = lambda;
+    TK_CHK(vec_lin2(rhs, rhs, sc2, zc, rhs, 1, n, st));
+    // CG on (J + lambda I) z = rhs
+    TK_CHK(vec_lin2(rhs, rhs, zc, zc, x, 1, n, st));
+    TK_CHK(vec_lin2(rhs, rhs, onec, zc, r, 1, n, st));
+    TK_CHK(vec_lin2(rhs, rhs, onec, zc, dv, 1, n, st));
+    TK_CHK(vec_dot(r, r, 0, sc, 1, n, st));
+    double rr;
+    TK_CHK(hipMemcpyAsync(&rr, sc, sizeof(double), hipMemcpyDeviceToHost, st));
+    TK_CHK(hipStreamSynchronize(st));
+    const double r0 = std::sqrt(rr);
+    const int maxit = max_cg > 0 ? max_cg : 5000;
+    const double tol = cg_tol > 0 ? cg_tol : 1e-12;
+    for (int j = 0; j < maxit && std::sqrt(rr) > tol * r0 && rr > 0; ++j) {
+        if ((rc = run_contract(d_K, dtype, n, m, d_alpha, dv, 1, nullptr, hd,
+                               dtype == TK_F64 ? ACC_PLAIN64 : ACC_PLAIN32, cw, cw_bytes, st)))
+            return rc;
+        TK_CHK(vec_shift_dot(dv, hd, lamc, sc, 1, n, st));
+        double dhd;
+        TK_CHK(hipMemcpyAsync(&dhd, sc, sizeof(double), hipMemcpyDeviceToHost, st));
+        TK_CHK(hipStreamSynchronize(st));
+        if (!(dhd > 0)) break;
+        Coefs a{};
+        a.c[0] = rr / dhd;
+        TK_CHK(vec_cg_update(x, r, dv, hd, a, sc, 1, n, st));
+        double rn;
+        TK_CHK(hipMemcpyAsync(&rn, sc, sizeof(double), hipMemcpyDeviceToHost, st));
+        TK_CHK(hipStreamSynchronize(st));
+        Coefs bc{};
+        bc.c[0] = rn / rr;
+        rr = rn;
+        TK_CHK(vec_lin2(r, dv, onec, bc, dv, 1, n, st));
+    }
+    // dMSE/dlambda = -z . alpha
+    TK_CHK(vec_dot(x, d_alpha, 0, sc, 1, n, st));
+    TK_CHK(hipMemcpyAsync(hs, sc, sizeof(double), hipMemcpyDeviceToHost, st));
+    TK_CHK(hipStreamSynchronize(st));
+    *h_dmse = -hs[0];
+    if (d_z) TK_CHK(hipMemcpyAsync(d_z, x, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+#undef TK_CHK
+    return TK_OK;
+}
+
+}  // extern "C"

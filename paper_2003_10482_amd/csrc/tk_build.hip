@@ -1,0 +1,164 @@
+// Build the packed tensor kernel (Section 4 kernels, Section 5 layout) on gfx950.
+//
+// Rows are the sorted (m-1)-tuples P in nested-loop order; row P holds the
+// entries K[P, l] for l in [P_last, n), contiguous in the packed array.  For the
+// linear kernel K[P, l] = sum_j q_P[j] x_l[j] with q_P = prod_{i in P} x_i
+// (elementwise), i.e. a product of the (rows x d) matrix Q with X^T restricted
+// to l >= P_last.  A workgroup computes a 64-row x 64-column tile: Q and X
+// chunks are staged in LDS and every thread accumulates a 4 x 4 register tile
+// in FP64 (VALU).  The kernel value (linear / polynomial / exponential) is
+// formed in FP64 and rounded once to the storage type.
+#include "tk_common.hpp"
+
+namespace tk {
+
+namespace {
+
+constexpr int TR = 64;    // rows per tile
+constexpr int TC = 64;    // columns per tile
+constexpr int FCH = 16;   // features per LDS chunk
+
+template <typename TOut>
+__device__ __forceinline__ void store_entry(void *K, int64_t i, double v);
+template <>
+__device__ __forceinline__ void store_entry<double>(void *K, int64_t i, double v)
+{
+    reinterpret_cast<double *>(K)[i] = v;
+}
+template <>
+__device__ __forceinline__ void store_entry<float>(void *K, int64_t i, double v)
+{
+    reinterpret_cast<float *>(K)[i] = (float)v;   // IEEE round-to-nearest-even
+}
+template <>
+__device__ __forceinline__ void store_entry<uint16_t>(void *K, int64_t i, double v)
+{
+    reinterpret_cast<uint16_t *>(K)[i] = double_to_bf16(v);
+}
+
+template <int M, typename TOut>
+__global__ void __launch_bounds__(256) build_kernel(const double *__restrict__ X, int n, int d,
+                                                    int kernel, double kparam, int64_t rows,
+                                                    void *K)
+{
+    constexpr int MP = M - 1;   // prefix length
+    __shared__ double qs[FCH][TR + 1];
+    __shared__ double xs[FCH][TC + 1];
+    __shared__ int pref[TR][MP > 0 ? MP : 1];
+    __shared__ int64_t roff[TR];
+    __shared__ int rk[TR];
+    __shared__ int kmin;
+
+    const int t = threadIdx.x;
+    const int64_t row0 = (int64_t)blockIdx.x * TR;
+    const int c0 = blockIdx.y * TC;
+    if (t == 0) kmin = n;
+    __syncthreads();
+    if (t < TR) {
+        const int64_t r = row0 + t;
+        int tup[M];
+        if (r < rows) {
+            if constexpr (MP > 0) unrank_tuple<MP>(r, n, tup);
+            const int k = MP > 0 ? tup[MP - 1] : 0;
+            tup[MP] = k;
+            roff[t] = rank_tuple<M>(tup, n);   // first entry of the row (l == k)
+            rk[t] = k;
+            for (int i = 0; i < MP; ++i) pref[t][i] = tup[i];
+            atomicMin(&kmin, k);
+        } else {
+            rk[t] = n;   // empty row
+            roff[t] = 0;
+            for (int i = 0; i < MP; ++i) pref[t][i] = 0;
+        }
+    }
+    __syncthreads();
+    if (kmin > c0 + TC - 1 || c0 >= n) return;   // every row starts right of this tile
+
+    const int tr = t / 16, tc = t % 16;   // 4x4 micro-tile
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+
+    for (int f0 = 0; f0 < d; f0 += FCH) {
+        // stage q_P[f] for the tile rows and x_l[f] for the tile columns
+        for (int i = t; i < TR * FCH; i += 256) {
+            const int r = i / FCH, f = i % FCH;
+            double q = 0.0;
+            if (f0 + f < d && rk[r] < n) {
+                q = 1.0;
+                for (int p = 0; p < MP; ++p) q *= X[(int64_t)pref[r][p] * d + f0 + f];
+            }
+            qs[f][r] = q;
+            const int l = c0 + r;
+            xs[f][r] = (f0 + f < d && l < n) ? X[(int64_t)l * d + f0 + f] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int f = 0; f < FCH; ++f) {
+            double qa[4], xb[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) qa[i] = qs[f][tr * 4 + i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) xb[j] = xs[f][tc * 4 + j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_fma(qa[i], xb[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = tr * 4 + i;
+        const int k = rk[r];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int l = c0 + tc * 4 + j;
+            if (l >= k && l < n) {
+                double v = acc[i][j];
+                if (kernel == TK_POLY) {
+                    const int s = (int)kparam;
+                    double pw = 1.0;
+                    for (int e = 0; e < s; ++e) pw *= v;
+                    v = pw;
+                } else if (kernel == TK_EXP) {
+                    v = exp(v);
+                }
+                store_entry<TOut>(K, roff[r] + (l - k), v);
+            }
+        }
+    }
+}
+
+template <int M>
+hipError_t launch_build_m(const double *X, int n, int d, int kernel, double kparam, int dtype,
+                          void *K, hipStream_t st)
+{
+    const int64_t rows = packed_count(n, M - 1);
+    dim3 grid((unsigned)((rows + TR - 1) / TR), (unsigned)((n + TC - 1) / TC));
+    if (dtype == TK_F64)
+        hipLaunchKernelGGL((build_kernel<M, double>), grid, dim3(256), 0, st, X, n, d, kernel, kparam, rows, K);
+    else if (dtype == TK_F32)
+        hipLaunchKernelGGL((build_kernel<M, float>), grid, dim3(256), 0, st, X, n, d, kernel, kparam, rows, K);
+    else
+        hipLaunchKernelGGL((build_kernel<M, uint16_t>), grid, dim3(256), 0, st, X, n, d, kernel, kparam, rows, K);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_build(const double *X, int n, int d, int m, int kernel, double kparam, int dtype,
+                        void *K, hipStream_t st)
+{
+    switch (m) {
+    case 2: return launch_build_m<2>(X, n, d, kernel, kparam, dtype, K, st);
+    case 4: return launch_build_m<4>(X, n, d, kernel, kparam, dtype, K, st);
+    case 6: return launch_build_m<6>(X, n, d, kernel, kparam, dtype, K, st);
+    case 8: return launch_build_m<8>(X, n, d, kernel, kparam, dtype, K, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace tk

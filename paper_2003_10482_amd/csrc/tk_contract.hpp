@@ -1,0 +1,43 @@
+// Host-visible pieces of the contraction kernels (parameters and launchers).
+#pragma once
+
+#include "tk_common.hpp"
+
+namespace tk {
+
+enum AccMode { ACC_DD = 0, ACC_PLAIN64 = 1, ACC_PLAIN32 = 2 };
+
+// One pass over an order-q packed array (levels q and q-1).
+struct PairParams {
+    const void *A;        // input array (storage type or intermediate type)
+    const void *Ad;       // tangent of the input array (lower passes of a derivative) or null
+    int64_t a_stride;     // entries between the per-vector input arrays (0: shared array)
+    int64_t count;        // entries of one input array: C(n+q-1, q)
+    int64_t units;        // C(n+q-3, q-2): leading (q-2)-tuples (1 when q == 2)
+    int64_t B;            // number of alpha vectors
+    int n;
+    double mu;            // integer multiplier of this pass (product of (q'-1) over earlier levels)
+    const double *alpha; // [B][n]
+    const double *vdir;  // [B][n] direction of the derivative (HV > 0)
+    void *S_out;         // [B][units] order q-2 array for the next pass (q >= 4)
+    void *Sd_out;        // its tangent
+    double *part;        // [B][groups][n] (hi, lo) column-sum partials, already scaled by mu
+    double *part_d;      // tangent partials
+};
+
+constexpr int kMaxPasses = kMaxOrder / 2;
+
+struct ReduceParams {
+    const double *part[kMaxPasses];
+    int groups[kMaxPasses];
+    int npass;
+    int n;
+    double *out;          // [B][n]
+};
+
+int pass_groups(int64_t count);
+hipError_t launch_pass(int q, int in_kind, int mode, int hv, int bt, const PairParams &pp,
+                       int groups, hipStream_t st);
+hipError_t launch_reduce(const ReduceParams &rp, int64_t B, hipStream_t st);
+
+}  // namespace tk

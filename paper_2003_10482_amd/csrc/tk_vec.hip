@@ -1,0 +1,200 @@
+// Small batched FP64 vector kernels used by the dual solve (gfx950).  Every
+// reduction is a fixed tree with compensated (double-double) partial sums, so
+// the solver's scalars are reproducible and accurate to about 2^-100.
+#include "tk_common.hpp"
+#include "tk_vec.hpp"
+
+namespace tk {
+
+namespace {
+
+__device__ DD block_sum_dd(DD v, DD *sh)
+{
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) sh[threadIdx.x] = dd_add(sh[threadIdx.x], sh[threadIdx.x + st]);
+        __syncthreads();
+    }
+    DD r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// grad_b = g_b + lam_b alpha_b - y ; stats_b = [alpha.g, alpha.alpha, y.alpha, grad.grad]
+__global__ void __launch_bounds__(256) grad_kernel(const double *__restrict__ g, const double *__restrict__ alpha,
+                                                   const double *__restrict__ y, Coefs lam,
+                                                   double *__restrict__ grad, double *__restrict__ stats,
+                                                   int64_t n)
+{
+    __shared__ DD sh[256];
+    const int b = blockIdx.x;
+    const double l = lam.c[b];
+    DD s_ag{0, 0}, s_aa{0, 0}, s_ya{0, 0}, s_gg{0, 0};
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const int64_t j = (int64_t)b * n + i;
+        const double a = alpha[j], gv = g[j], yv = y[i];
+        // grad = g + lam a - y, formed with one rounding of the exact sum
+        DD t{0, 0};
+        dd_fma(t, l, a);
+        DD u = dd_add(t, DD{gv, 0.0});
+        u = dd_add(u, DD{-yv, 0.0});
+        const double gr = u.hi + u.lo;
+        grad[j] = gr;
+        dd_fma(s_ag, a, gv);
+        dd_fma(s_aa, a, a);
+        dd_fma(s_ya, yv, a);
+        dd_fma(s_gg, gr, gr);
+    }
+    DD r0 = block_sum_dd(s_ag, sh), r1 = block_sum_dd(s_aa, sh), r2 = block_sum_dd(s_ya, sh),
+       r3 = block_sum_dd(s_gg, sh);
+    if (threadIdx.x == 0) {
+        stats[b * 4 + 0] = r0.hi + r0.lo;
+        stats[b * 4 + 1] = r1.hi + r1.lo;
+        stats[b * 4 + 2] = r2.hi + r2.lo;
+        stats[b * 4 + 3] = r3.hi + r3.lo;
+    }
+}
+
+// out_b = x_b . y_b (both [B][n]; y_stride 0 broadcasts one vector)
+__global__ void __launch_bounds__(256) dot_kernel(const double *__restrict__ x, const double *__restrict__ y,
+                                                  int64_t y_stride, double *__restrict__ out, int64_t n)
+{
+    __shared__ DD sh[256];
+    const int b = blockIdx.x;
+    DD s{0, 0};
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) dd_fma(s, x[(int64_t)b * n + i], y[(int64_t)b * y_stride + i]);
+    DD r = block_sum_dd(s, sh);
+    if (threadIdx.x == 0) out[b] = r.hi + r.lo;
+}
+
+// z_b = a_b x_b + c_b y_b   (z may alias x or y)
+__global__ void __launch_bounds__(256) lin2_kernel(const double *x, const double *y, Coefs a, Coefs c,
+                                                   double *z, int64_t n)
+{
+    const int b = blockIdx.y;
+    const double ab = a.c[b], cb = c.c[b];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = (int64_t)b * n + i;
+        z[j] = __builtin_fma(ab, x[j], cb * y[j]);
+    }
+}
+
+// Hd_b += lam_b d_b ; out_b = d_b . Hd_b
+__global__ void __launch_bounds__(256) shift_dot_kernel(const double *__restrict__ dvec, double *__restrict__ hd,
+                                                        Coefs lam, double *__restrict__ out, int64_t n)
+{
+    __shared__ DD sh[256];
+    const int b = blockIdx.x;
+    DD s{0, 0};
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const int64_t j = (int64_t)b * n + i;
+        const double v = __builtin_fma(lam.c[b], dvec[j], hd[j]);
+        hd[j] = v;
+        dd_fma(s, dvec[j], v);
+    }
+    DD r = block_sum_dd(s, sh);
+    if (threadIdx.x == 0) out[b] = r.hi + r.lo;
+}
+
+// x_b += a_b d_b ; r_b -= a_b Hd_b ; out_b = r_b . r_b
+__global__ void __launch_bounds__(256) cg_update_kernel(double *__restrict__ x, double *__restrict__ r,
+                                                        const double *__restrict__ dvec,
+                                                        const double *__restrict__ hd, Coefs a,
+                                                        double *__restrict__ out, int64_t n)
+{
+    __shared__ DD sh[256];
+    const int b = blockIdx.x;
+    const double ab = a.c[b];
+    DD s{0, 0};
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const int64_t j = (int64_t)b * n + i;
+        x[j] = __builtin_fma(ab, dvec[j], x[j]);
+        const double rv = __builtin_fma(-ab, hd[j], r[j]);
+        r[j] = rv;
+        dd_fma(s, rv, rv);
+    }
+    DD q = block_sum_dd(s, sh);
+    if (threadIdx.x == 0) out[b] = q.hi + q.lo;
+}
+
+// elementwise v = u^(p) * s  (u, s [B][d] or broadcast), used by the dMSE gradient
+__global__ void pow_mul_kernel(const double *__restrict__ u, const double *__restrict__ s, int p,
+                               double *__restrict__ out, int64_t len)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x) {
+        double pw = 1.0;
+        for (int e = 0; e < p; ++e) pw *= u[i];
+        out[i] = pw * s[i];
+    }
+}
+
+__global__ void sub_kernel(const double *__restrict__ a, const double *__restrict__ b, double *__restrict__ out,
+                           int64_t len)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = a[i] - b[i];
+}
+
+__global__ void nonfinite_kernel(const double *__restrict__ x, int64_t len, int *__restrict__ flag)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x)
+        if (!isfinite(x[i])) atomicOr(flag, 1);
+}
+
+inline unsigned grid_for(int64_t n)
+{
+    int64_t g = (n + 255) / 256;
+    return (unsigned)(g < 1 ? 1 : g > 1024 ? 1024 : g);
+}
+
+}  // namespace
+
+hipError_t vec_grad(const double *g, const double *alpha, const double *y, const Coefs &lam,
+                    double *grad, double *stats, int64_t B, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(grad_kernel, dim3((unsigned)B), dim3(256), 0, st, g, alpha, y, lam, grad, stats, n);
+    return hipGetLastError();
+}
+hipError_t vec_dot(const double *x, const double *y, int64_t y_stride, double *out, int64_t B, int64_t n,
+                   hipStream_t st)
+{
+    hipLaunchKernelGGL(dot_kernel, dim3((unsigned)B), dim3(256), 0, st, x, y, y_stride, out, n);
+    return hipGetLastError();
+}
+hipError_t vec_lin2(const double *x, const double *y, const Coefs &a, const Coefs &c, double *z, int64_t B,
+                    int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(lin2_kernel, dim3(grid_for(n) > 8 ? 8 : grid_for(n), (unsigned)B), dim3(256), 0, st, x, y,
+                       a, c, z, n);
+    return hipGetLastError();
+}
+hipError_t vec_shift_dot(const double *d, double *hd, const Coefs &lam, double *out, int64_t B, int64_t n,
+                         hipStream_t st)
+{
+    hipLaunchKernelGGL(shift_dot_kernel, dim3((unsigned)B), dim3(256), 0, st, d, hd, lam, out, n);
+    return hipGetLastError();
+}
+hipError_t vec_cg_update(double *x, double *r, const double *d, const double *hd, const Coefs &a, double *out,
+                         int64_t B, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(cg_update_kernel, dim3((unsigned)B), dim3(256), 0, st, x, r, d, hd, a, out, n);
+    return hipGetLastError();
+}
+hipError_t vec_pow_mul(const double *u, const double *s, int p, double *out, int64_t len, hipStream_t st)
+{
+    hipLaunchKernelGGL(pow_mul_kernel, dim3(grid_for(len)), dim3(256), 0, st, u, s, p, out, len);
+    return hipGetLastError();
+}
+hipError_t vec_sub(const double *a, const double *b, double *out, int64_t len, hipStream_t st)
+{
+    hipLaunchKernelGGL(sub_kernel, dim3(grid_for(len)), dim3(256), 0, st, a, b, out, len);
+    return hipGetLastError();
+}
+hipError_t vec_nonfinite(const double *x, int64_t len, int *flag, hipStream_t st)
+{
+    hipLaunchKernelGGL(nonfinite_kernel, dim3(grid_for(len)), dim3(256), 0, st, x, len, flag);
+    return hipGetLastError();
+}
+
+}  // namespace tk

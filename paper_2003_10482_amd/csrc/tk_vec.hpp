@@ -1,0 +1,29 @@
+// Batched FP64 vector kernels of the dual solve.
+#pragma once
+
+#include "tk_common.hpp"
+
+namespace tk {
+
+constexpr int kMaxCoefs = 64;   // vectors per launch of a coefficient-carrying kernel
+
+struct Coefs {
+    double c[kMaxCoefs];
+};
+
+hipError_t vec_grad(const double *g, const double *alpha, const double *y, const Coefs &lam,
+                    double *grad, double *stats, int64_t B, int64_t n, hipStream_t st);
+hipError_t vec_dot(const double *x, const double *y, int64_t y_stride, double *out, int64_t B,
+                   int64_t n, hipStream_t st);
+hipError_t vec_lin2(const double *x, const double *y, const Coefs &a, const Coefs &c, double *z,
+                    int64_t B, int64_t n, hipStream_t st);
+hipError_t vec_shift_dot(const double *d, double *hd, const Coefs &lam, double *out, int64_t B,
+                         int64_t n, hipStream_t st);
+hipError_t vec_cg_update(double *x, double *r, const double *d, const double *hd, const Coefs &a,
+                         double *out, int64_t B, int64_t n, hipStream_t st);
+hipError_t vec_pow_mul(const double *u, const double *s, int p, double *out, int64_t len,
+                       hipStream_t st);
+hipError_t vec_sub(const double *a, const double *b, double *out, int64_t len, hipStream_t st);
+hipError_t vec_nonfinite(const double *x, int64_t len, int *flag, hipStream_t st);
+
+}  // namespace tk

@@ -1,0 +1,178 @@
+"""GPU parity of the packed build, contraction and directional derivative
+against the CPU oracle, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2003_10482_amd as tk
+from gpu_util import U32, U64, UBF16, abs_terms, device, to_dev, to_np
+from oracle import dual as D
+from oracle import layout as L
+from oracle import precision as P
+from oracle import tensor as T
+from synth import make_workload, random_alpha, random_symmetric_packed_values
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(1, 4), (3, 2), (9, 2), (7, 4), (20, 4), (70, 4), (130, 4), (5, 6), (12, 6), (64, 6), (70, 6)]
+
+
+def _packed_dev(Kh, n, m, dtype="f64"):
+    dt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[dtype]
+    if dtype == "bf16":
+        bits = np.array([P.round_bf16_scalar(x) for x in Kh]) if Kh.size < 200000 else P.round_bf16(Kh)
+        t = torch.tensor(bits, dtype=torch.float64).to(torch.float32).to(torch.bfloat16)
+        return tk.PackedTensor(t.to(device()), n, m, tk.BF16), bits
+    if dtype == "f32":
+        r = P.round_fp32(Kh)
+        return tk.PackedTensor(torch.tensor(r, dtype=torch.float32, device=device()), n, m, tk.F32), r
+    return tk.PackedTensor(to_dev(Kh), n, m, tk.F64), Kh
+
+
+def _dyadic_X(n, d, seed):
+    # entries k/16: products and sums of up to 64 terms are exact in FP64, but
+    # need more significant bits than FP32 or BF16 hold
+    rng = np.random.default_rng(seed)
+    return rng.integers(-40, 41, size=(n, d)) / 16.0
+
+
+@pytest.mark.parametrize("n,m", [(12, 4), (70, 4), (9, 6), (66, 6), (30, 2), (256, 4)])
+def test_build_exact_and_rounded(n, m):
+    d = 24
+    X = _dyadic_X(n, d, seed=n + m)
+    Kref = T.build_packed(X, m)          # exact in FP64 for these inputs
+    Xd = to_dev(X)
+    K64 = tk.build_packed_tensor(Xd, m, dtype="f64")
+    np.testing.assert_array_equal(to_np(K64.data), Kref)
+    K32 = tk.build_packed_tensor(Xd, m, dtype="f32")
+    np.testing.assert_array_equal(to_np(K32.data).astype(np.float64), P.round_fp32(Kref))
+    Kb = tk.build_packed_tensor(Xd, m, dtype="bf16")
+    np.testing.assert_array_equal(to_np(Kb.data.to(torch.float32)).astype(np.float64), P.round_bf16(Kref))
+
+
+@pytest.mark.parametrize("kernel,kparam", [("poly", 2), ("exp", 0.0)])
+def test_build_poly_exp(kernel, kparam):
+    n, d, m = 11, 6, 4
+    X = 0.4 * np.random.default_rng(3).standard_normal((n, d))
+    Kref = T.build_packed(X, m, kernel, kparam)
+    K = tk.build_packed_tensor(to_dev(X), m, kernel=kernel, kparam=kparam)
+    np.testing.assert_allclose(to_np(K.data), Kref, rtol=1e-13, atol=1e-15)
+
+
+def test_build_sampled_entries_config2():
+    """Full-size build (n=256, d=200, m=4): sampled entries, each recomputed
+    alone by the oracle, and the entry count."""
+    wl = make_workload("c2_n256_m4")
+    K = tk.build_packed_tensor(to_dev(wl.X), 4)
+    assert K.data.numel() == L.packed_count(256, 4) == 183181376
+    rng = np.random.default_rng(0)
+    idx = np.concatenate([rng.integers(0, K.data.numel(), 300), [0, K.data.numel() - 1]])
+    got = to_np(K.data[torch.as_tensor(idx, device=device())])
+    for e, v in zip(idx.tolist(), got.tolist()):
+        t = L.unrank(e, 256, 4)
+        ref = T.kernel_entry(wl.X, t)
+        bound = 4 * 200 * U64 * T.kernel_entry(np.abs(wl.X), t)
+        assert abs(v - ref) <= bound + 1e-300
+
+
+@pytest.mark.parametrize("n,m", SHAPES)
+@pytest.mark.parametrize("acc", [tk.ACC_COMPENSATED, tk.ACC_F64])
+def test_contract_f64_random_tensor(n, m, acc):
+    K = random_symmetric_packed_values(L.packed_count(n, m), seed=10 * n + m)
+    B = 3
+    A = random_alpha(n, seed=n + 100 * m, batch=B)
+    Kd, _ = _packed_dev(K, n, m)
+    g = to_np(tk.contract(Kd, to_dev(A), acc=acc))
+    for b in range(B):
+        ref = T.contract_packed(K, n, m, A[b])
+        E = abs_terms(K, n, m, A[b])
+        # both sides are sums of the same terms; each errs by at most its depth x u x E
+        depth = L.packed_count(n, m - 1) + 4 * n + 64
+        assert np.all(np.abs(g[b] - ref) <= 2 * depth * U64 * E + 1e-300), (n, m, b)
+        np.testing.assert_allclose(g[b], ref, rtol=1e-10, atol=1e-12 * E.max())
+
+
+@pytest.mark.parametrize("n,m", [(20, 4), (70, 4), (200, 4), (12, 6), (64, 6)])
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_contract_reduced_precision(n, m, storage):
+    K = random_symmetric_packed_values(L.packed_count(n, m), seed=7 * n + m)
+    B = 5
+    A = random_alpha(n, seed=3 * n + m, batch=B)
+    Kd, Kr = _packed_dev(K, n, m, storage)
+    g = to_np(tk.contract(Kd, to_dev(A)))
+    us = U32 if storage == "f32" else UBF16
+    for b in range(B):
+        ref = T.contract_packed(K, n, m, A[b])
+        E = abs_terms(K, n, m, A[b])
+        # a-priori bound: storage rounding of K, FP32 rounding of alpha and of each
+        # product (m+1 factors), and FP32 accumulation along chains of at most
+        # (rows of the order m array + 4n + 64) additions
+        depth = L.packed_count(n, m - 1) + 4 * n + 64
+        bound = (us + (m + 2) * U32 + depth * U32) * E
+        assert np.all(np.abs(g[b] - ref) <= bound), (n, m, storage, b)
+        # typical error: the same result computed from the rounded tensor in FP64
+        ref_r = T.contract_packed(Kr, n, m, A[b])
+        assert np.max(np.abs(g[b] - ref_r) / E) <= 64 * U32 * np.sqrt(depth)
+
+
+@pytest.mark.parametrize("n,m", [(7, 4), (70, 4), (130, 4), (5, 6), (64, 6), (9, 2)])
+def test_hvp_f64_random_tensor(n, m):
+    K = random_symmetric_packed_values(L.packed_count(n, m), seed=n * m + 1)
+    B = 2
+    A = random_alpha(n, seed=n + 1, batch=B)
+    V = random_alpha(n, seed=n + 2, batch=B)
+    Kd, _ = _packed_dev(K, n, m)
+    h, g = tk.hvp(Kd, to_dev(A), to_dev(V), with_g=True)
+    h, g = to_np(h), to_np(g)
+    for b in range(B):
+        ref_h = T.hvp_packed(K, n, m, A[b], V[b])
+        ref_g = T.contract_packed(K, n, m, A[b])
+        Eh = T.hvp_packed(np.abs(K), n, m, np.abs(A[b]), np.abs(V[b]))
+        np.testing.assert_allclose(h[b], ref_h, rtol=1e-9, atol=1e-11 * Eh.max())
+        np.testing.assert_allclose(g[b], ref_g, rtol=1e-9, atol=1e-11 * abs_terms(K, n, m, A[b]).max())
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_hvp_reduced_precision(storage):
+    n, m = 70, 4
+    K = random_symmetric_packed_values(L.packed_count(n, m), seed=5)
+    A = random_alpha(n, seed=6, batch=5)
+    V = random_alpha(n, seed=7, batch=5)
+    Kd, Kr = _packed_dev(K, n, m, storage)
+    h = to_np(tk.hvp(Kd, to_dev(A), to_dev(V)))
+    for b in range(5):
+        ref = T.hvp_packed(Kr, n, m, A[b], V[b])
+        Eh = T.hvp_packed(np.abs(K), n, m, np.abs(A[b]), np.abs(V[b]))
+        assert np.max(np.abs(h[b] - ref) / Eh.max()) <= 1e-4
+
+
+def test_contract_compensated_at_dual_optimum():
+    """Near the dual optimum the packed sum cancels by ~9 orders of magnitude;
+    the compensated FP64 kernel still matches the exact closed form
+    X (X^T alpha)^{m-1} of the linear kernel (eq. tensor_1), which the oracle's
+    own plain FP64 packed sum does not."""
+    wl = make_workload("c1_n64_m4")
+    a, _ = D.solve_linear(wl.X, wl.y, wl.lam, wl.m)
+    ref = T.contract_closed(wl.X, a, wl.m)
+    K = tk.build_packed_tensor(to_dev(wl.X), wl.m)
+    g = to_np(tk.contract(K, to_dev(a)))
+    assert np.max(np.abs(g - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_contract_deterministic():
+    n, m = 130, 4
+    K = random_symmetric_packed_values(L.packed_count(n, m), seed=1)
+    Kd, _ = _packed_dev(K, n, m)
+    a = to_dev(random_alpha(n, seed=2, batch=2))
+    g1 = tk.contract(Kd, a)
+    g2 = tk.contract(Kd, a)
+    assert torch.equal(g1, g2)
+
+
+def test_dense_shortcut_matches_closed_form():
+    wl = make_workload("c2_n256_m4")
+    A = random_alpha(256, seed=9, batch=3)
+    g = to_np(tk.contract_dense(to_dev(wl.X), to_dev(A), 4))
+    for b in range(3):
+        ref = T.contract_closed(wl.X, A[b], 4)
+        np.testing.assert_allclose(g[b], ref, rtol=1e-11, atol=1e-12 * np.abs(ref).max())
