@@ -78,7 +78,7 @@ ContractPlan make_plan(int64_t n, int m, int64_t B, int mode, bool hv)
         p.q = q;
         p.count = packed_count(n, q);
         p.units = q >= 4 ? packed_count(n, q - 2) : 1;
-        p.groups = pass_groups(p.count);
+        p.groups = pass_groups(q, n, p.count);
         p.s_bytes = q >= 4 ? align256((size_t)B * p.units * inter_size(mode)) : 0;
         p.s_off = off;
         off += p.s_bytes * (hv ? 2 : 1);
@@ -134,8 +134,11 @@ int run_contract(const void *K, int dtype, int64_t n, int m, const double *alpha
         prm.Sd_out = (pp.s_bytes && hv) ? w + pp.s_off + pp.s_bytes : nullptr;
         prm.part = reinterpret_cast<double *>(w + pp.p_off);
         prm.part_d = hv ? reinterpret_cast<double *>(w + pp.p_off + pp.p_bytes) : nullptr;
+        int perr = 0;
+        prm.plan = pass_plan(pp.q, n, pp.groups, &perr);
+        if (perr || !prm.plan) return fail(TK_EHIP, "could not place the work plan of pass q=%d", pp.q);
         const int hvl = hv ? (i == 0 ? 1 : 2) : 0;
-        const int bt = (i == 0 && mode == ACC_PLAIN32) ? 4 : 1;
+        const int bt = (i == 0 && mode == ACC_PLAIN32 && B >= 4) ? 4 : 1;
         hipError_t e = launch_pass(pp.q, in_kind, mode, hvl, bt, prm, pp.groups, st);
         if (e != hipSuccess) return fail(TK_EHIP, "contraction pass q=%d failed: %s", pp.q, hipGetErrorString(e));
         rv.part[i] = prm.part;

@@ -24,6 +24,11 @@
 // heavy cancellation of the contraction near the dual optimum does not eat the
 // FP64 result), plain FP64, plain FP32.  The directional derivative runs the
 // same recursion on dual numbers alpha + eps v.
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
 #include "tk_common.hpp"
 #include "tk_contract.hpp"
 
@@ -54,6 +59,8 @@ struct ModeT<ACC_PLAIN32> {
 // ----------------------------------------------------- accumulator ops ----
 __device__ __forceinline__ void acc_fma(DD &a, DD c, double v) { dd_fma(a, c, v); }
 __device__ __forceinline__ void acc_fma(DD &a, DD c, DD v) { dd_fma(a, c, v); }
+__device__ __forceinline__ void acc_fma(DD &a, double c, double v) { dd_fma(a, c, v); }
+__device__ __forceinline__ void acc_fma(DD &a, double c, DD v) { dd_fma(a, v, c); }
 __device__ __forceinline__ void acc_fma(double &a, double c, double v) { a = __builtin_fma(c, v, a); }
 __device__ __forceinline__ void acc_fma(float &a, float c, float v) { a = __builtin_fmaf(c, v, a); }
 
@@ -79,14 +86,24 @@ template <int MODE>
 struct Coef {
     using T = typename ModeT<MODE>::V;
     __device__ __forceinline__ static T make(double x) { return (T)x; }
-    __device__ __forceinline__ static T div(T a, int r) { return a / (T)r; }
+    __device__ __forceinline__ static T div(T a, int r)
+    {
+        if (r == 1) return a;
+        if (r == 2) return a * (T)0.5;
+        return a / (T)r;
+    }
     __device__ __forceinline__ static T mul(T a, T b) { return a * b; }
 };
 template <>
 struct Coef<ACC_DD> {
     using T = DD;
     __device__ __forceinline__ static DD make(double x) { return DD{x, 0.0}; }
-    __device__ __forceinline__ static DD div(DD a, int r) { return r == 1 ? a : dd_div_int(a, (double)r); }
+    __device__ __forceinline__ static DD div(DD a, int r)
+    {
+        if (r == 1) return a;
+        if (r == 2) return DD{a.hi * 0.5, a.lo * 0.5};   // exact
+        return dd_div_int(a, (double)r);
+    }
     __device__ __forceinline__ static DD mul(DD a, DD b) { return dd_mul(a, b); }
 };
 
@@ -103,7 +120,7 @@ struct In<double, MODE> {
     using R = typename ModeT<MODE>::V;
     __device__ __forceinline__ static R load(const void *p, int64_t i)
     {
-        return (R) __builtin_nontemporal_load(reinterpret_cast<const double *>(p) + i);
+        return (R) reinterpret_cast<const double *>(p)[i];
     }
 };
 template <int MODE>
@@ -111,7 +128,7 @@ struct In<float, MODE> {
     using R = typename ModeT<MODE>::V;
     __device__ __forceinline__ static R load(const void *p, int64_t i)
     {
-        return (R) __builtin_nontemporal_load(reinterpret_cast<const float *>(p) + i);
+        return (R) reinterpret_cast<const float *>(p)[i];
     }
 };
 template <int MODE>
@@ -119,7 +136,7 @@ struct In<uint16_t, MODE> {
     using R = typename ModeT<MODE>::V;
     __device__ __forceinline__ static R load(const void *p, int64_t i)
     {
-        return (R)bf16_to_float(__builtin_nontemporal_load(reinterpret_cast<const uint16_t *>(p) + i));
+        return (R)bf16_to_float(reinterpret_cast<const uint16_t *>(p)[i]);
     }
 };
 template <>
@@ -187,11 +204,17 @@ __global__ void __launch_bounds__(256) pair_kernel(PairParams p)
     V *vdir_s = alpha_s + BT * p.n;                           // [BT][n] (HVP)
     const int n = p.n;
     const int lane = threadIdx.x & (kWave - 1);
-    const int wid = threadIdx.x / kWave;
+    // the wave index is uniform across the wave: keep it (and all the unit and
+    // row bookkeeping derived from it) in scalar registers
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     size_t stage_bytes = (size_t)BT * n * sizeof(V) * (HVP ? 2 : 1);
     stage_bytes = (stage_bytes + 15) & ~(size_t)15;
     PT *buf = reinterpret_cast<PT *>(smem + stage_bytes) + (size_t)wid * (RB * NC * kWave + RB * NC);
     PT *sbatch = buf + RB * NC * kWave;                      // [RB][NC] row sums of a batch
+    // column sums across units (times the unit multipliers), one slot per lane
+    PT *colw = reinterpret_cast<PT *>(smem + stage_bytes) + (size_t)(blockDim.x / kWave) * (RB * NC * kWave + RB * NC) +
+               (size_t)wid * (BT * NB * kWave * (HVP ? 2 : 1));
+    PT *coldw = colw + BT * NB * kWave;
 
     const int b0 = blockIdx.y * BT;      // first alpha vector of this tile
     // per-vector arrays (lower passes, BT == 1) sit a_stride entries apart
@@ -213,7 +236,6 @@ __global__ void __launch_bounds__(256) pair_kernel(PairParams p)
 
     // per-lane column state: l = 64 b + lane
     V a_l[BT][NB], v_l[BT][NB];
-    PT col[BT][NB], cold[BT][NB];     // column sums across units (x unit multiplier)
     PT U[BT][NB], Ud[BT][NB];         // column sums within the current unit
 #pragma unroll
     for (int bt = 0; bt < BT; ++bt)
@@ -222,62 +244,34 @@ __global__ void __launch_bounds__(256) pair_kernel(PairParams p)
             const int l = b * kWave + lane;
             a_l[bt][b] = l < n ? alpha_s[bt * n + l] : V(0);
             v_l[bt][b] = (HVP && l < n) ? vdir_s[bt * n + l] : V(0);
-            col[bt][b] = p_zero<PT>();
-            cold[bt][b] = p_zero<PT>();
+            colw[(bt * NB + b) * kWave + lane] = p_zero<PT>();
+            if constexpr (HVP) coldw[(bt * NB + b) * kWave + lane] = p_zero<PT>();
         }
 
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wid;
-    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
-    const int64_t e_lo = wave * p.count / nwaves;
-    const int64_t e_hi = (wave + 1) * p.count / nwaves;
+    // work plan: wave w owns units (Q >= 4) or rows (Q == 2) [plan[w], plan[w+1]),
+    // cut on the host so that every wave gets the same modelled cost
+    const int64_t u_lo = p.plan[wave];
+    const int64_t u_hi = p.plan[wave + 1];
+    bool active = u_lo < u_hi;
 
-    // ---- locate the first unit (Q >= 4) or row (Q == 2) starting in [e_lo, e_hi)
     int P[QP > 0 ? QP : 1];
-    int64_t uidx = 0, ustart = 0;
+    int64_t uidx = u_lo, ustart = 0;
     int k_first = 0, k_end = n;
-    bool active = e_lo < e_hi;
     if constexpr (QP > 0) {
-        int t[Q];
-        if (active)
-            unrank_tuple<Q>(e_lo, n, t);
-        else
-            for (int i = 0; i < Q; ++i) t[i] = 0;
+        if (active) {
+            unrank_tuple<QP>(u_lo, n, P);
+            int tt[Q];
 #pragma unroll
-        for (int i = 0; i < QP; ++i) P[i] = t[i];
-        int tt[Q];
-#pragma unroll
-        for (int i = 0; i < QP; ++i) tt[i] = P[i];
-        tt[QP] = tt[QP + 1] = P[QP - 1];
-        ustart = rank_tuple<Q>(tt, n);
-        uidx = rank_tuple<QP>(P, n);
-        if (active && ustart < e_lo) {
-            // advance to the next unit in nested-loop order
-            const int64_t kk = P[QP - 1];
-            ustart += (n - kk) * (n - kk + 1) / 2;
-            int pos = QP - 1;
-            while (pos >= 0 && P[pos] == n - 1) --pos;
-            if (pos < 0) {
-                active = false;
-            } else {
-                P[pos] += 1;
-                for (int i = pos + 1; i < QP; ++i) P[i] = P[pos];
-                uidx += 1;
-            }
+            for (int i = 0; i < QP; ++i) tt[i] = P[i];
+            tt[QP] = tt[QP + 1] = P[QP - 1];
+            ustart = rank_tuple<Q>(tt, n);
         }
     } else {
-        // Q == 2: one unit, waves split its rows.  Row k starts at k n - k(k-1)/2.
-        int t[2];
-        if (active) {
-            unrank_tuple<2>(e_lo, n, t);
-            int k = t[0];
-            if ((int64_t)k * n - (int64_t)k * (k - 1) / 2 < e_lo) ++k;
-            k_first = k;
-            int u[2];
-            unrank_tuple<2>(e_hi - 1, n, u);
-            k_end = u[0] + 1;
-            if (k_first >= k_end) active = false;
-            ustart = (int64_t)k_first * n - (int64_t)k_first * (k_first - 1) / 2;
-        }
+        // Q == 2: one unit, the wave owns rows [u_lo, u_hi); row k starts at k n - k(k-1)/2
+        k_first = (int)u_lo;
+        k_end = (int)u_hi;
+        ustart = (int64_t)k_first * n - (int64_t)k_first * (k_first - 1) / 2;
     }
 
     // ---- loop over units
@@ -285,7 +279,7 @@ __global__ void __launch_bounds__(256) pair_kernel(PairParams p)
         int k0, rr;
         CT Cu[BT], Cud[BT];        // unit multiplier (q-1)!/prod r_p(P') alpha^{P'} and its tangent
         if constexpr (QP > 0) {
-            if (ustart >= e_hi || uidx >= p.units) break;
+            if (uidx >= u_hi) break;
             k0 = P[QP - 1];
             int run = 1;
             double wden = 1.0;
@@ -329,6 +323,15 @@ __global__ void __launch_bounds__(256) pair_kernel(PairParams p)
         }
         const int k_lo = (QP > 0) ? k0 : k_first;
         const int k_hi = (QP > 0) ? n : k_end;
+        // 1/r, alpha_k0/r and v_k0/r for the unit's first row (r = rr)
+        const CT inv_rr = Coef<MODE>::div(Coef<MODE>::make(1.0), rr);
+        CT ak0_rr[BT], vk0_rr[BT];
+#pragma unroll
+        for (int bt = 0; bt < BT; ++bt) {
+            ak0_rr[bt] = Coef<MODE>::div(Coef<MODE>::make((double)alpha_s[bt * n + k0]), rr);
+            vk0_rr[bt] = HVP ? Coef<MODE>::div(Coef<MODE>::make((double)vdir_s[bt * n + k0]), rr)
+                             : Coef<MODE>::make(0.0);
+        }
 
 #pragma unroll
         for (int bt = 0; bt < BT; ++bt)
@@ -368,18 +371,14 @@ __global__ void __launch_bounds__(256) pair_kernel(PairParams p)
                     }
                 }
             }
-            // ---- phase 2: row partials and in-unit column sums
+            // ---- phase 2: row partials and in-unit column sums.  Only the block
+            // holding the diagonal entry l == k carries the tie factor 1/(r_k+1).
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
                 if (r >= nrows) break;
                 const int k = kb0 + r;
+                const int kb = k >> 6;
                 const int rk = (QP > 0 && k == k0) ? rr : 1;          // r_{Q-1}(P', k)
-                PT part[BT], partd[BT];
-#pragma unroll
-                for (int bt = 0; bt < BT; ++bt) {
-                    part[bt] = p_zero<PT>();
-                    partd[bt] = p_zero<PT>();
-                }
 #pragma unroll
                 for (int bt = 0; bt < BT; ++bt) {
                     const V ak = alpha_s[bt * n + k];
@@ -393,34 +392,46 @@ __global__ void __launch_bounds__(256) pair_kernel(PairParams p)
                         cud_tie = Coef<MODE>::div(cud, rk + 1);
                         vk_tie = Coef<MODE>::div(Coef<MODE>::make((double)vk), rk + 1);
                     }
+                    PT part = p_zero<PT>(), partd = p_zero<PT>();
 #pragma unroll
                     for (int b = 0; b < NB; ++b) {
-                        if (b < (k >> 6)) continue;
+                        if (b < kb) continue;
                         const int l = b * kWave + lane;
                         const VIn x = val[r][b];
-                        const bool tie = (b == (k >> 6)) && (l == k);
-                        const CT cU = tie ? cu_tie : cu;
-                        const CT cP = tie ? ck_tie : Coef<MODE>::make((double)a_l[bt][b]);
-                        acc_cv(U[bt][b], cU, x);
-                        acc_cv(part[bt], cP, x);
-                        if constexpr (HVP) {
-                            const VIn xd = vald[r][b];
-                            const CT cUd = tie ? cud_tie : cud;
-                            const CT cPd = tie ? vk_tie : Coef<MODE>::make((double)v_l[bt][b]);
-                            acc_cv(Ud[bt][b], cUd, x);
-                            acc_cv(partd[bt], cPd, x);
-                            if constexpr (ATAN) {
-                                acc_cv(Ud[bt][b], cU, xd);
-                                acc_cv(partd[bt], cP, xd);
+                        if (b == kb) {
+                            const bool tie = (l == k);
+                            const CT cU = tie ? cu_tie : cu;
+                            const CT cP = tie ? ck_tie : Coef<MODE>::make((double)a_l[bt][b]);
+                            acc_cv(U[bt][b], cU, x);
+                            acc_cv(part, cP, x);
+                            if constexpr (HVP) {
+                                const VIn xd = vald[r][b];
+                                const CT cUd = tie ? cud_tie : cud;
+                                const CT cPd = tie ? vk_tie : Coef<MODE>::make((double)v_l[bt][b]);
+                                acc_cv(Ud[bt][b], cUd, x);
+                                acc_cv(partd, cPd, x);
+                                if constexpr (ATAN) {
+                                    acc_cv(Ud[bt][b], cU, xd);
+                                    acc_cv(partd, cP, xd);
+                                }
+                            }
+                        } else {
+                            acc_cv(U[bt][b], cu, x);
+                            acc_cv(part, a_l[bt][b], x);
+                            if constexpr (HVP) {
+                                const VIn xd = vald[r][b];
+                                acc_cv(Ud[bt][b], cud, x);
+                                acc_cv(partd, v_l[bt][b], x);
+                                if constexpr (ATAN) {
+                                    acc_cv(Ud[bt][b], cu, xd);
+                                    acc_cv(partd, a_l[bt][b], xd);
+                                }
                             }
                         }
                     }
-                }
-#pragma unroll
-                for (int bt = 0; bt < BT; ++bt) {
-                    buf[(r * NC + bt) * kWave + lane] = part[bt];
+                    buf[(r * NC + bt) * kWave + lane] = part;
                     if constexpr (HVP)
-                        buf[(r * NC + BT + bt) * kWave + lane] = partd[bt];
+                        buf[(r * NC + BT + bt) * kWave + lane] = partd;
                 }
             }
             __builtin_amdgcn_wave_barrier();
@@ -441,25 +452,29 @@ __global__ void __launch_bounds__(256) pair_kernel(PairParams p)
                 }
             }
             __builtin_amdgcn_wave_barrier();
-            // ---- level Q-1: S_{P',k}/r_k joins the column sums at index k; S_{P'} partial
+            // ---- level Q-1: S_{P',k}/r_k joins the column sums at index k; S_{P'} partial.
+            // r_k = rr only for the unit's first row (k == k0), 1 otherwise.
+            const int bfirst = kb0 >> 6, blast = (kb0 + nrows - 1) >> 6;
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
+                if (b < bfirst || b > blast) continue;   // blocks holding no row of the batch
                 const int k = b * kWave + lane;
                 if (k >= kb0 && k < kb0 + nrows) {
                     const int r = k - kb0;
-                    const int rk = (QP > 0 && k == k0) ? rr : 1;
+                    const bool first = (QP > 0) && (k == k0);
 #pragma unroll
                     for (int bt = 0; bt < BT; ++bt) {
                         const PT s = sbatch[r * NC + bt];
-                        const CT inv = Coef<MODE>::div(Coef<MODE>::make(1.0), rk);
+                        const CT one = Coef<MODE>::make(1.0);
+                        const CT inv = first ? inv_rr : one;
                         acc_cv(U[bt][b], inv, s);
                         // S_{P'} += S_k alpha_k / r_k
-                        const CT ak = Coef<MODE>::div(Coef<MODE>::make((double)a_l[bt][b]), rk);
+                        const CT ak = first ? ak0_rr[bt] : Coef<MODE>::make((double)a_l[bt][b]);
                         acc_cv(unitS[bt], ak, s);
                         if constexpr (HVP) {
                             const PT sd = sbatch[r * NC + BT + bt];
                             acc_cv(Ud[bt][b], inv, sd);
-                            const CT vk = Coef<MODE>::div(Coef<MODE>::make((double)v_l[bt][b]), rk);
+                            const CT vk = first ? vk0_rr[bt] : Coef<MODE>::make((double)v_l[bt][b]);
                             acc_cv(unitSd[bt], ak, sd);
                             acc_cv(unitSd[bt], vk, s);
                         }
@@ -475,10 +490,14 @@ __global__ void __launch_bounds__(256) pair_kernel(PairParams p)
         for (int bt = 0; bt < BT; ++bt)
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
-                acc_unit(col[bt][b], Cu[bt], U[bt][b]);
+                PT c = colw[(bt * NB + b) * kWave + lane];
+                acc_unit(c, Cu[bt], U[bt][b]);
+                colw[(bt * NB + b) * kWave + lane] = c;
                 if constexpr (HVP) {
-                    acc_unit(cold[bt][b], Cud[bt], U[bt][b]);
-                    acc_unit(cold[bt][b], Cu[bt], Ud[bt][b]);
+                    PT cd = coldw[(bt * NB + b) * kWave + lane];
+                    acc_unit(cd, Cud[bt], U[bt][b]);
+                    acc_unit(cd, Cu[bt], Ud[bt][b]);
+                    coldw[(bt * NB + b) * kWave + lane] = cd;
                 }
             }
         if constexpr (QP > 0) {
@@ -511,15 +530,18 @@ __global__ void __launch_bounds__(256) pair_kernel(PairParams p)
 
     // ---- workgroup reduction of the column sums, scaled by mu, to partials
     __syncthreads();
-    PT *red = reinterpret_cast<PT *>(smem + stage_bytes);   // reuse: [waves][NC][NB*64]
+    // the per-wave column sums sit after the batch buffers; gather them into the
+    // (now free) batch-buffer region as [waves][NC][NB*64] and reduce
+    PT *red = reinterpret_cast<PT *>(smem + stage_bytes);
     const int nw = blockDim.x / kWave;
 #pragma unroll
     for (int bt = 0; bt < BT; ++bt)
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            red[((size_t)wid * NC + bt) * (NB * kWave) + b * kWave + lane] = col[bt][b];
+            red[((size_t)wid * NC + bt) * (NB * kWave) + b * kWave + lane] = colw[(bt * NB + b) * kWave + lane];
             if constexpr (HVP)
-                red[((size_t)wid * NC + BT + bt) * (NB * kWave) + b * kWave + lane] = cold[bt][b];
+                red[((size_t)wid * NC + BT + bt) * (NB * kWave) + b * kWave + lane] =
+                    coldw[(bt * NB + b) * kWave + lane];
         }
     __syncthreads();
     for (int i = threadIdx.x; i < NC * n; i += blockDim.x) {
@@ -598,8 +620,10 @@ constexpr int batch_rows()
     using PT = typename ModeT<MODE>::P;
     constexpr int NC = BT * (HVP ? 2 : 1);
     constexpr int bytes = NC * kWave * (int)sizeof(PT);
-    constexpr int rb = 8192 / bytes;
-    return rb >= 8 ? 8 : rb >= 4 ? 4 : 2;
+    constexpr int rb0 = 8192 / bytes;
+    constexpr int rb = rb0 >= 8 ? 8 : rb0 >= 4 ? 4 : 2;
+    // the load buffer holds RB x NB values per lane: keep it at <= 16 entries
+    return (rb * NB > 16) ? (16 / NB >= 2 ? 16 / NB : 2) : rb;
 }
 
 template <int Q, int NB, typename TIn, int MODE, int HV, int BT>
@@ -613,8 +637,10 @@ hipError_t launch_pair(const PairParams &pp, int groups, int btiles, hipStream_t
     size_t stage = (size_t)BT * pp.n * sizeof(V) * (HVP ? 2 : 1);
     stage = (stage + 15) & ~(size_t)15;
     const size_t per_wave = (size_t)(RB * NC * kWave + RB * NC) * sizeof(PT);
+    const size_t cols = (size_t)4 * BT * NB * kWave * (HVP ? 2 : 1) * sizeof(PT);
     const size_t red = (size_t)4 * NC * NB * kWave * sizeof(PT);
-    const size_t lds = stage + (per_wave * 4 > red ? per_wave * 4 : red);
+    if (red > per_wave * 4 + cols) return hipErrorInvalidValue;
+    const size_t lds = stage + per_wave * 4 + cols;
     auto kern = pair_kernel<Q, NB, TIn, MODE, HV, BT, RB>;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)kern,
@@ -659,11 +685,104 @@ hipError_t dispatch_q(int q, const PairParams &pp, int groups, int bt, hipStream
 
 }  // namespace
 
-// Number of workgroups of one pass over an order-q array of `count` entries.
-int pass_groups(int64_t count)
+
+// ------------------------------------------------------------ work plans ----
+// Modelled cost of one row (fixed part plus one term per 64-column block it
+// touches) and of one unit (fixed part).  The weights approximate the
+// instruction counts of the kernel; only their ratios matter.
+namespace {
+constexpr double kCostRow = 6.0, kCostBlock = 8.0, kCostBatch = 4.0, kCostUnit = 60.0;
+
+std::vector<int64_t> make_plan_host(int q, int64_t n, int64_t waves)
 {
-    // about 16K entries per wave, at most 3 resident workgroups per CU on 256 CUs
-    int64_t g = (count + 4 * 16384 - 1) / (4 * 16384);
+    const int nb = (int)((n + kWave - 1) / kWave);
+    // cost of the rows k in [k0, n) of a unit whose leading indices end at k0
+    std::vector<double> tail(n + 1, 0.0);
+    for (int64_t k = n - 1; k >= 0; --k) tail[k] = tail[k + 1] + kCostRow + kCostBlock * (nb - (k >> 6));
+    std::vector<int64_t> plan(waves + 1, 0);
+    if (q == 2) {
+        double total = tail[0];
+        int64_t w = 1;
+        double acc = 0.0;
+        for (int64_t k = 0; k < n && w < waves; ++k) {
+            acc += kCostRow + kCostBlock * (nb - (k >> 6));
+            while (w < waves && acc >= total * (double)w / (double)waves) plan[w++] = k + 1;
+        }
+        while (w <= waves) plan[w++] = n;
+        plan[waves] = n;
+        return plan;
+    }
+    const int qp = q - 2;
+    auto unit_cost = [&](int k0) {
+        const double rows = (double)(n - k0);
+        return tail[k0] + kCostBatch * std::ceil(rows / 4.0) + kCostUnit;
+    };
+    // units in nested-loop order; only the last index matters for the cost
+    std::vector<int> t(qp, 0);
+    double total = 0.0;
+    int64_t units = 0;
+    while (true) {
+        total += unit_cost(t[qp - 1]);
+        ++units;
+        int pos = qp - 1;
+        while (pos >= 0 && t[pos] == n - 1) --pos;
+        if (pos < 0) break;
+        t[pos] += 1;
+        for (int i = pos + 1; i < qp; ++i) t[i] = t[pos];
+    }
+    std::fill(t.begin(), t.end(), 0);
+    int64_t w = 1, u = 0;
+    double acc = 0.0;
+    while (u < units && w < waves) {
+        acc += unit_cost(t[qp - 1]);
+        ++u;
+        while (w < waves && acc >= total * (double)w / (double)waves) plan[w++] = u;
+        int pos = qp - 1;
+        while (pos >= 0 && t[pos] == n - 1) --pos;
+        if (pos < 0) break;
+        t[pos] += 1;
+        for (int i = pos + 1; i < qp; ++i) t[i] = t[pos];
+    }
+    while (w <= waves) plan[w++] = units;
+    plan[waves] = units;
+    return plan;
+}
+
+std::mutex g_plan_mu;
+std::map<std::tuple<int, int, int64_t, int>, int64_t *> g_plans;
+}  // namespace
+
+const int64_t *pass_plan(int q, int64_t n, int groups, int *err)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        *err = 1;
+        return nullptr;
+    }
+    const auto key = std::make_tuple(dev, q, n, groups);
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    auto it = g_plans.find(key);
+    if (it != g_plans.end()) return it->second;
+    const std::vector<int64_t> h = make_plan_host(q, n, (int64_t)groups * 4);
+    int64_t *d = nullptr;
+    if (hipMalloc((void **)&d, h.size() * sizeof(int64_t)) != hipSuccess ||
+        hipMemcpy(d, h.data(), h.size() * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess) {
+        *err = 1;
+        return nullptr;
+    }
+    g_plans[key] = d;
+    return d;
+}
+
+// Number of workgroups of one pass over an order-q array of `count` entries.
+int pass_groups(int q, int64_t n, int64_t count)
+{
+    if (q == 2) {   // waves split the rows of the single unit: a few rows per wave
+        int64_t g = (n + 15) / 16;
+        return (int)(g < 1 ? 1 : g);
+    }
+    // about 4K entries per wave, at most 3 resident workgroups per CU on 256 CUs
+    int64_t g = (count + 4 * 4096 - 1) / (4 * 4096);
     if (g < 1) g = 1;
     if (g > 768) g = 768;
     return (int)g;

@@ -23,6 +23,7 @@ struct PairParams {
     void *Sd_out;        // its tangent
     double *part;        // [B][groups][n] (hi, lo) column-sum partials, already scaled by mu
     double *part_d;      // tangent partials
+    const int64_t *plan; // [waves + 1] first unit (q >= 4) or row (q == 2) of every wave
 };
 
 constexpr int kMaxPasses = kMaxOrder / 2;
@@ -35,7 +36,9 @@ struct ReduceParams {
     double *out;          // [B][n]
 };
 
-int pass_groups(int64_t count);
+int pass_groups(int q, int64_t n, int64_t count);
+// Device copy of the balanced work plan of one pass (cached per (n, q, groups)).
+const int64_t *pass_plan(int q, int64_t n, int groups, int *err);
 hipError_t launch_pass(int q, int in_kind, int mode, int hv, int bt, const PairParams &pp,
                        int groups, hipStream_t st);
 hipError_t launch_reduce(const ReduceParams &rp, int64_t B, hipStream_t st);

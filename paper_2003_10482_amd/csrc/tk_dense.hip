@@ -15,7 +15,8 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // of C; the K loop feeds v_mfma_f64_16x16x4f64 four k at a time:
 //   A operand: lane holds A[row0 + lane%16][k0 + lane/16]
 //   B operand: lane holds B[k0 + lane/16][col0 + lane%16]
-//   result:    lane holds C[row0 + 4*(lane/16) + j][col0 + lane%16], j = 0..3
+//   result:    lane holds C[row0 + 4*j + lane/16][col0 + lane%16], j = 0..3
+//              (checked on the device with one-hot operands)
 __global__ void __launch_bounds__(256) gemm_f64_mfma(const double *__restrict__ A, int64_t lda,
                                                      const double *__restrict__ Bm, int64_t bsk,
                                                      int64_t bsj, double *__restrict__ C,
@@ -40,7 +41,7 @@ __global__ void __launch_bounds__(256) gemm_f64_mfma(const double *__restrict__ 
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const int64_t r = row0 + 4 * (lane >> 4) + j;
+        const int64_t r = row0 + 4 * j + (lane >> 4);
         const int64_t c = col0 + (lane & 15);
         if (r < M && c < N) {
             double v = acc[j];
