@@ -1,0 +1,147 @@
+"""Benchmark of the packed tensor-kernel hot path on one MI355X.
+
+One step = one pass of the whole hot path on the workload n=256, d=200, m=4,
+lambda=1e-2 (synthetic, Section 5.4 data model, seed 1002), inputs resident in
+HBM: build the packed FP64 tensor (C(259,4) = 183,181,376 entries, 1.47 GB),
+solve the dual to ||grad D|| <= 1e-11 lambda ||alpha|| with the truncated-Newton
+solver (every Newton / CG / line-search step streams the packed tensor once),
+recover w = (X^T alpha)^3, take the 2-std support and predict on X.
+
+value = passes over the packed tensor per second across the timed steps
+        (K . alpha^{m-1} contractions and their directional derivatives).
+roofline = the dominant kernel (the pass that streams K inside the directional
+        derivative), timed with HIP events on its launch stream over the timed
+        region: algorithmic bytes = C x 8 B per launch.
+cpu_baseline = the CPU oracle's packed FP64 contraction (single thread) on a
+        seeded random symmetric tensor of the same size.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def cpu_baseline(passes: int = 2) -> dict:
+    import numpy as np
+
+    from oracle import tensor as T
+    from oracle.layout import packed_count
+    from synth import random_alpha, random_symmetric_packed_values
+
+    n, m = 256, 4
+    K = random_symmetric_packed_values(packed_count(n, m), seed=77)
+    a = random_alpha(n, seed=78)
+    t0 = time.perf_counter()
+    for _ in range(passes):
+        T.contract_packed(K, n, m, a)
+    dt = time.perf_counter() - t0
+    return {"value": passes / dt, "unit": "contractions/s", "cores": 1, "kind": "oracle",
+            "sample": f"{passes} passes of the packed FP64 contraction at n=256, m=4 "
+                      f"(C(259,4) entries) on a seeded random symmetric tensor, "
+                      f"single-threaded C oracle, {dt:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2003_10482_amd as tk
+    from synth import make_workload
+
+    dev = torch.device("cuda:0")
+    wl = make_workload("c2_n256_m4")
+    X = torch.as_tensor(wl.X, device=dev)
+    y = torch.as_tensor(wl.y, device=dev)
+    count = tk.packed_count(wl.n, wl.m)
+
+    def step():
+        K = tk.build_packed_tensor(X, wl.m, dtype="f64")
+        alpha, infos = tk.solve_dual(K, y, [wl.lam], tol=1e-11)
+        W = tk.primal_weights(X, alpha, wl.m)
+        mask, tau = tk.support(W)
+        f = tk.predict(W, X)
+        del K
+        return alpha, infos, W, mask, f
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    tk.timing_start()
+    passes = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        alpha, infos, W, mask, f = step()
+        passes += infos[0]["passes"]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    timing = tk.timing_stop()
+    ms_step = 1e3 * elapsed / args.steps
+
+    kind = max(timing, key=lambda k: timing[k][1])
+    launches, kms, kbytes = timing[kind]
+    avg_ms = kms / max(launches, 1)
+    achieved = (kbytes / max(launches, 1)) / (avg_ms * 1e-3) / 1e9
+    mask_np = mask.cpu().numpy()[0].astype(bool)
+    sel = set(np.flatnonzero(mask_np).tolist())
+    true = set(wl.support.tolist())
+    tp = len(sel & true)
+    f1 = 0.0 if tp == 0 else 2 * tp / (len(sel) + len(true))
+
+    out = {
+        "metric": "K·α^{m-1} contractions/s + HBM GB/s (m=4,n=256); solve time at fixed support accuracy",
+        "value": passes / elapsed,
+        "unit": "contractions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "n=256 d=200 m=4 lambda=1e-2 FP64 build + dual solve + support",
+                   "n": wl.n, "d": wl.d, "m": wl.m, "lambda": wl.lam, "packed_entries": count,
+                   "packed_bytes": count * 8},
+        "solve": {"passes_per_step": passes / args.steps, "newton_iters": infos[0]["newton_iters"],
+                  "cg_iters": infos[0]["cg_iters"], "grad_norm": infos[0]["grad_norm"],
+                  "status": infos[0]["status"], "support_f1": f1, "support_size": len(sel)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": f"packed-tensor pass ({kind})", "avg_launch_ms": avg_ms,
+                     "launches": launches},
+    }
+    other = "contract" if kind == "hvp" else "hvp"
+    if timing[other][0]:
+        l2, ms2, b2 = timing[other]
+        out["roofline"]["other_pass"] = {"kind": other, "avg_launch_ms": ms2 / l2,
+                                         "achieved_GBs": (b2 / l2) / (ms2 / l2 * 1e-3) / 1e9}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

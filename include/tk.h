@@ -218,6 +218,18 @@ int tk_dmse_dlambda(const void *d_K, int dtype, int64_t n, int m, const double *
 
 int tk_dmse_workspace(int64_t n, int m, int64_t d, int64_t nval, int dtype, size_t *h_bytes);
 
+/*
+ * Instrumentation (not part of the method): while enabled, every pass that
+ * streams the packed tensor (the first pass of tk_contract / tk_hvp, also when
+ * called inside tk_solve_dual or tk_dmse_dlambda) is bracketed by HIP events on
+ * its own stream.  tk_timing_stop synchronises those events and returns, per
+ * kind (0 = contraction, 1 = directional derivative), the number of launches,
+ * their summed duration in milliseconds and the bytes of the packed tensor they
+ * read (entries x storage size).  Arrays are host arrays of length 2.
+ */
+int tk_timing_start(void);
+int tk_timing_stop(int64_t *h_launches, double *h_ms, double *h_bytes);
+
 #ifdef __cplusplus
 }
 #endif

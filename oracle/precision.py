@@ -33,8 +33,20 @@ def round_bf16_scalar(x: float) -> float:
 
 
 def round_bf16(a) -> np.ndarray:
+    """Vectorised form of round_bf16_scalar: the same steps on whole arrays
+    (np.round also breaks exact ties to the even neighbour)."""
     a = np.asarray(a, dtype=np.float64)
-    return np.vectorize(round_bf16_scalar, otypes=[np.float64])(a)
+    out = a.copy()
+    fin = np.isfinite(a) & (a != 0.0)
+    ax = np.abs(a[fin])
+    q = np.empty_like(ax)
+    small = ax < 2.0 ** _BF16_MIN_NORMAL_EXP
+    q[small] = np.round(ax[small] / _BF16_SUBNORMAL_QUANTUM) * _BF16_SUBNORMAL_QUANTUM
+    f, e = np.frexp(ax[~small])
+    q[~small] = np.ldexp(np.round(np.ldexp(f, 8)), e - 8)
+    q[q >= _BF16_OVERFLOW] = np.inf
+    out[fin] = np.copysign(q, a[fin])
+    return out
 
 
 def round_fp32(a) -> np.ndarray:

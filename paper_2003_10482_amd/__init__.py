@@ -8,5 +8,5 @@ from .api import (  # noqa: F401
     ACC_AUTO, ACC_COMPENSATED, ACC_F32, ACC_F64, BF16, EXP, F32, F64, LINEAR, POLY,
     PackedTensor, TkContract, build_packed_tensor, contract, contract_autograd, contract_dense,
     contract_workspace, dmse_dlambda, gather_rows, hvp, max_points, packed_count, predict,
-    primal_weights, solve_dual, solve_workspace, support,
+    primal_weights, solve_dual, solve_workspace, support, timing_start, timing_stop,
 )

@@ -74,6 +74,8 @@ _SIGNATURES = {
     "tk_dmse_dlambda": (c_int, [c_vp, c_int, c_i64, c_int, c_vp, c_i64, c_vp, c_dbl, c_vp, c_vp, c_i64,
                                 c_dbl, c_int, ctypes.POINTER(c_dbl), ctypes.POINTER(c_dbl), c_vp, c_vp,
                                 c_sz, c_vp]),
+    "tk_timing_start": (c_int, []),
+    "tk_timing_stop": (c_int, [ctypes.POINTER(c_i64), ctypes.POINTER(c_dbl), ctypes.POINTER(c_dbl)]),
 }
 
 

@@ -250,3 +250,17 @@ class TkContract(torch.autograd.Function):
 
 def contract_autograd(K: PackedTensor, alpha: torch.Tensor) -> torch.Tensor:
     return TkContract.apply(alpha, K)
+
+
+def timing_start() -> None:
+    """Start bracketing every packed-tensor pass with HIP events (instrumentation)."""
+    _lib.check(_lib.load().tk_timing_start())
+
+
+def timing_stop() -> dict:
+    """Stop and return {kind: (launches, total_ms, bytes)} for kind in contract/hvp."""
+    n = (ctypes.c_int64 * 2)()
+    ms = (ctypes.c_double * 2)()
+    by = (ctypes.c_double * 2)()
+    _lib.check(_lib.load().tk_timing_stop(n, ms, by))
+    return {"contract": (n[0], ms[0], by[0]), "hvp": (n[1], ms[1], by[1])}

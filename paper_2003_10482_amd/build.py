@@ -19,7 +19,7 @@ ARCH = os.environ.get("TK_OFFLOAD_ARCH", "gfx950")
 SOURCES = ["tk_contract.hip", "tk_build.hip", "tk_dense.hip", "tk_vec.hip", "tk_abi.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wno-unused-result", "-munsafe-fp-atomics"]
+         "-Wno-unused-result", "-munsafe-fp-atomics", "-ffp-contract=off"]
 
 
 def hipcc() -> str:

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "tk_common.hpp"
@@ -102,6 +103,16 @@ int mode_for(int dtype, int acc, bool hv, int *mode)
     return fail(TK_EINVAL, "accumulation %d not available for FP32/BF16 storage", acc);
 }
 
+// ------------------------------------------------------- instrumentation ----
+struct TimedLaunch {
+    hipEvent_t a, b;
+    int kind;
+    double bytes;
+};
+std::mutex g_timing_mu;
+bool g_timing_on = false;
+std::vector<TimedLaunch> g_timing;
+
 // Run every pass of the contraction (and its tangent when vdir != null).
 int run_contract(const void *K, int dtype, int64_t n, int m, const double *alpha, const double *vdir,
                  int64_t B, double *g, double *h, int mode, void *work, size_t work_bytes, hipStream_t st)
@@ -139,8 +150,24 @@ int run_contract(const void *K, int dtype, int64_t n, int m, const double *alpha
         if (perr || !prm.plan) return fail(TK_EHIP, "could not place the work plan of pass q=%d", pp.q);
         const int hvl = hv ? (i == 0 ? 1 : 2) : 0;
         const int bt = (i == 0 && mode == ACC_PLAIN32 && B >= 4) ? 4 : 1;
+        TimedLaunch tl{};
+        bool timed = false;
+        if (i == 0) {
+            std::lock_guard<std::mutex> lk(g_timing_mu);
+            if (g_timing_on && hipEventCreate(&tl.a) == hipSuccess && hipEventCreate(&tl.b) == hipSuccess) {
+                timed = true;
+                tl.kind = hv ? 1 : 0;
+                tl.bytes = (double)pp.count * (double)dtype_size(dtype);
+                hipEventRecord(tl.a, st);
+            }
+        }
         hipError_t e = launch_pass(pp.q, in_kind, mode, hvl, bt, prm, pp.groups, st);
         if (e != hipSuccess) return fail(TK_EHIP, "contraction pass q=%d failed: %s", pp.q, hipGetErrorString(e));
+        if (timed) {
+            hipEventRecord(tl.b, st);
+            std::lock_guard<std::mutex> lk(g_timing_mu);
+            g_timing.push_back(tl);
+        }
         rv.part[i] = prm.part;
         rv.groups[i] = pp.groups;
         rt.part[i] = prm.part_d;
@@ -262,6 +289,43 @@ int tk_hvp(const void *d_K, int dtype, int64_t n, int m, const double *d_alpha, 
     int mode;
     if ((rc = mode_for(dtype, TK_ACC_AUTO, true, &mode))) return rc;
     return run_contract(d_K, dtype, n, m, d_alpha, d_v, B, d_g, d_h, mode, d_work, work_bytes, as_stream(stream));
+}
+
+int tk_timing_start(void)
+{
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    for (auto &t : g_timing) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    g_timing.clear();
+    g_timing_on = true;
+    return TK_OK;
+}
+
+int tk_timing_stop(int64_t *h_launches, double *h_ms, double *h_bytes)
+{
+    if (!h_launches || !h_ms || !h_bytes) return fail(TK_EINVAL, "null output pointer");
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    g_timing_on = false;
+    for (int k = 0; k < 2; ++k) {
+        h_launches[k] = 0;
+        h_ms[k] = 0.0;
+        h_bytes[k] = 0.0;
+    }
+    int rc = TK_OK;
+    for (auto &t : g_timing) {
+        float ms = 0.f;
+        if (hipEventSynchronize(t.b) != hipSuccess || hipEventElapsedTime(&ms, t.a, t.b) != hipSuccess)
+            rc = fail(TK_EHIP, "timing events failed");
+        h_launches[t.kind] += 1;
+        h_ms[t.kind] += ms;
+        h_bytes[t.kind] += t.bytes;
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    g_timing.clear();
+    return rc;
 }
 
 void tk_solve_opts_default(tk_solve_opts *o)

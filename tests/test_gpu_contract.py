@@ -14,13 +14,13 @@ from synth import make_workload, random_alpha, random_symmetric_packed_values
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(1, 4), (3, 2), (9, 2), (7, 4), (20, 4), (70, 4), (130, 4), (5, 6), (12, 6), (64, 6), (70, 6)]
+SHAPES = [(1, 4), (3, 2), (9, 2), (7, 4), (20, 4), (70, 4), (130, 4), (5, 6), (12, 6), (40, 6), (66, 6)]
 
 
 def _packed_dev(Kh, n, m, dtype="f64"):
     dt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[dtype]
     if dtype == "bf16":
-        bits = np.array([P.round_bf16_scalar(x) for x in Kh]) if Kh.size < 200000 else P.round_bf16(Kh)
+        bits = P.round_bf16(Kh)
         t = torch.tensor(bits, dtype=torch.float64).to(torch.float32).to(torch.bfloat16)
         return tk.PackedTensor(t.to(device()), n, m, tk.BF16), bits
     if dtype == "f32":
@@ -36,9 +36,9 @@ def _dyadic_X(n, d, seed):
     return rng.integers(-40, 41, size=(n, d)) / 16.0
 
 
-@pytest.mark.parametrize("n,m", [(12, 4), (70, 4), (9, 6), (66, 6), (30, 2), (256, 4)])
+@pytest.mark.parametrize("n,m", [(12, 4), (70, 4), (9, 6), (66, 6), (30, 2), (150, 4)])
 def test_build_exact_and_rounded(n, m):
-    d = 24
+    d = 16
     X = _dyadic_X(n, d, seed=n + m)
     Kref = T.build_packed(X, m)          # exact in FP64 for these inputs
     Xd = to_dev(X)
@@ -79,7 +79,7 @@ def test_build_sampled_entries_config2():
 @pytest.mark.parametrize("acc", [tk.ACC_COMPENSATED, tk.ACC_F64])
 def test_contract_f64_random_tensor(n, m, acc):
     K = random_symmetric_packed_values(L.packed_count(n, m), seed=10 * n + m)
-    B = 3
+    B = 3 if L.packed_count(n, m) < 10 ** 6 else 1
     A = random_alpha(n, seed=n + 100 * m, batch=B)
     Kd, _ = _packed_dev(K, n, m)
     g = to_np(tk.contract(Kd, to_dev(A), acc=acc))
@@ -92,11 +92,11 @@ def test_contract_f64_random_tensor(n, m, acc):
         np.testing.assert_allclose(g[b], ref, rtol=1e-10, atol=1e-12 * E.max())
 
 
-@pytest.mark.parametrize("n,m", [(20, 4), (70, 4), (200, 4), (12, 6), (64, 6)])
+@pytest.mark.parametrize("n,m", [(20, 4), (70, 4), (200, 4), (12, 6), (40, 6)])
 @pytest.mark.parametrize("storage", ["f32", "bf16"])
 def test_contract_reduced_precision(n, m, storage):
     K = random_symmetric_packed_values(L.packed_count(n, m), seed=7 * n + m)
-    B = 5
+    B = 5 if L.packed_count(n, m) < 10 ** 7 else 2
     A = random_alpha(n, seed=3 * n + m, batch=B)
     Kd, Kr = _packed_dev(K, n, m, storage)
     g = to_np(tk.contract(Kd, to_dev(A)))
@@ -115,7 +115,7 @@ def test_contract_reduced_precision(n, m, storage):
         assert np.max(np.abs(g[b] - ref_r) / E) <= 64 * U32 * np.sqrt(depth)
 
 
-@pytest.mark.parametrize("n,m", [(7, 4), (70, 4), (130, 4), (5, 6), (64, 6), (9, 2)])
+@pytest.mark.parametrize("n,m", [(7, 4), (70, 4), (130, 4), (5, 6), (40, 6), (9, 2)])
 def test_hvp_f64_random_tensor(n, m):
     K = random_symmetric_packed_values(L.packed_count(n, m), seed=n * m + 1)
     B = 2
@@ -156,7 +156,7 @@ def test_contract_compensated_at_dual_optimum():
     ref = T.contract_closed(wl.X, a, wl.m)
     K = tk.build_packed_tensor(to_dev(wl.X), wl.m)
     g = to_np(tk.contract(K, to_dev(a)))
-    assert np.max(np.abs(g - ref)) <= 1e-12 * np.max(np.abs(ref))
+    assert np.max(np.abs(g - ref)) <= 2e-14 * np.max(np.abs(ref))
 
 
 def test_contract_deterministic():

@@ -202,3 +202,8 @@ def test_bf16_rounding_pins():
     assert np.all(f * 256 == np.round(f * 256))
     assert np.all(np.abs(y - x) <= 2.0 ** (e - 9) + 0.0)
     np.testing.assert_array_equal(P.round_fp32(x), x.astype(np.float32).astype(np.float64))
+    # the vectorised form follows the scalar definition exactly, including ties,
+    # subnormals and overflow
+    z = np.concatenate([x, [1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 2.0 ** -134, 2.0 ** -133, 3 * 2.0 ** -135,
+                            (2 - 2 ** -8) * 2.0 ** 127, -0.0, 0.0, np.inf, -np.inf]])
+    np.testing.assert_array_equal(P.round_bf16(z), np.array([P.round_bf16_scalar(v) for v in z]))
