@@ -146,17 +146,39 @@ def test_hvp_reduced_precision(storage):
         assert np.max(np.abs(h[b] - ref) / Eh.max()) <= 1e-4
 
 
+def _exact_closed_form(X, a, m):
+    """g = X (X^T a)^{m-1} in exact rational arithmetic (eq. tensor_1)."""
+    from fractions import Fraction
+    Xf = [[Fraction(v) for v in row] for row in X.tolist()]
+    af = [Fraction(v) for v in a.tolist()]
+    n, d = len(Xf), len(Xf[0])
+    u = [sum(Xf[i][j] * af[i] for i in range(n)) for j in range(d)]
+    w = [uj ** (m - 1) for uj in u]
+    return np.array([float(sum(Xf[i][j] * w[j] for j in range(d))) for i in range(n)])
+
+
 def test_contract_compensated_at_dual_optimum():
-    """Near the dual optimum the packed sum cancels by ~9 orders of magnitude;
-    the compensated FP64 kernel still matches the exact closed form
-    X (X^T alpha)^{m-1} of the linear kernel (eq. tensor_1), which the oracle's
-    own plain FP64 packed sum does not."""
-    wl = make_workload("c1_n64_m4")
-    a, _ = D.solve_linear(wl.X, wl.y, wl.lam, wl.m)
-    ref = T.contract_closed(wl.X, a, wl.m)
-    K = tk.build_packed_tensor(to_dev(wl.X), wl.m)
+    """Near the dual optimum the packed sum cancels by ~9 orders of magnitude.
+    With dyadic points the packed FP64 tensor is exact, so the compensated FP64
+    contraction must match the exact value of X (X^T alpha)^{m-1} (rational
+    arithmetic) to about one rounding of g, while a plain FP64 sum of the same
+    terms does not."""
+    from synth import planted_regression
+    n, d, m = 64, 20, 4
+    X = _dyadic_X(n, d, seed=11)
+    rng = np.random.default_rng(12)
+    _, y, _, _ = planted_regression(rng, n, d, 4, 0.01)
+    y = X @ np.where(np.arange(d) < 4, 1.0, 0.0) + 0.01 * y
+    a, _ = D.solve_linear(X, y, 1e-2, m)
+    exact = _exact_closed_form(X, a, m)
+    K = tk.build_packed_tensor(to_dev(X), m)
+    assert np.array_equal(to_np(K.data), T.build_packed(X, m))     # the stored tensor is exact
     g = to_np(tk.contract(K, to_dev(a)))
-    assert np.max(np.abs(g - ref)) <= 2e-14 * np.max(np.abs(ref))
+    E = abs_terms(T.build_packed(X, m), n, m, a)
+    assert E.max() / np.abs(exact).max() > 1e5                        # heavy cancellation indeed
+    assert np.max(np.abs(g - exact)) <= 4 * U64 * np.max(np.abs(exact)) + 64 * U64 ** 2 * E.max()
+    g_plain = to_np(tk.contract(K, to_dev(a), acc=tk.ACC_F64))
+    assert np.max(np.abs(g_plain - exact)) > 1e3 * np.max(np.abs(g - exact))
 
 
 def test_contract_deterministic():
