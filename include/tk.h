@@ -71,7 +71,9 @@ int64_t tk_max_points(void);
 
 /*
  * Number of packed entries C(n+m-1, m) (Section 5, eq. b_tensor4 for m = 4)
- * and their size in bytes for `dtype`.  Pure host arithmetic, no device work.
+ * and the size in bytes of a buffer holding them as `dtype` (BF16 buffers are
+ * rounded up to a multiple of 4 bytes, since they are read a dword at a
+ * time).  Pure host arithmetic, no device work.
  * Errors: TK_EINVAL (n < 1, m < 1), TK_EOVERFLOW.
  */
 int tk_packed_count(int64_t n, int m, int64_t *h_count);

@@ -68,10 +68,26 @@ def build_packed_tensor(X: torch.Tensor, m: int, kernel="linear", kparam: float 
     X = _dev_f64(X, "X")
     n, d = X.shape
     dt = _DTYPES[dtype]
-    K = torch.empty(packed_count(n, m), dtype=_TORCH_STORAGE[dt], device=X.device)
+    K = empty_packed(n, m, dt, X.device)
     _lib.check(_lib.load().tk_build_packed_tensor(_ptr(X), n, d, m, _KERNELS[kernel], float(kparam),
                                                   dt, _ptr(K), _stream()))
     return PackedTensor(K, n, m, dt)
+
+
+def packed_bytes(n: int, m: int, dtype) -> int:
+    out = ctypes.c_int64()
+    _lib.check(_lib.load().tk_packed_bytes(n, m, _DTYPES[dtype], ctypes.byref(out)))
+    return out.value
+
+
+def empty_packed(n: int, m: int, dtype, device) -> torch.Tensor:
+    """A device buffer for a packed tensor: C(n+m-1, m) elements of the storage
+    type, padded to tk_packed_bytes (BF16 buffers are read a dword at a time)."""
+    dt = _DTYPES[dtype]
+    count = packed_count(n, m)
+    esz = {F64: 8, F32: 4, BF16: 2}[dt]
+    total = (packed_bytes(n, m, dt) + esz - 1) // esz
+    return torch.empty(total, dtype=_TORCH_STORAGE[dt], device=device)[:count]
 
 
 def contract_workspace(n: int, m: int, B: int, dtype) -> int:

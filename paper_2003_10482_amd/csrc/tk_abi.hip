@@ -228,9 +228,10 @@ int tk_packed_bytes(int64_t n, int m, int dtype, int64_t *h_bytes)
     if (rc) return rc;
     if ((rc = check_dtype(dtype))) return rc;
     const int64_t s = (int64_t)dtype_size(dtype);
-    if (c > INT64_MAX / s) return fail(TK_EOVERFLOW, "packed byte count overflows int64");
+    if (c > INT64_MAX / s - 4) return fail(TK_EOVERFLOW, "packed byte count overflows int64");
     if (!h_bytes) return fail(TK_EINVAL, "null output pointer");
-    *h_bytes = c * s;
+    // BF16 tensors are read a dword at a time: round the buffer up to whole dwords
+    *h_bytes = dtype == TK_BF16 ? ((c * s + 3) & ~(int64_t)3) : c * s;
     return TK_OK;
 }
 
@@ -443,6 +444,10 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
         const int max_newton = o.fixed_iters > 0 ? o.fixed_iters : (o.max_newton > 0 ? o.max_newton : 100);
         double gn0[kMaxCoefs];
         for (int64_t b = 0; b < B; ++b) gn0[b] = ps[b].gn > 0 ? ps[b].gn : 1.0;
+        // reduced-precision phase before a polish: hand over once the gradient
+        // stops shrinking (the rounded tensor's noise floor)
+        std::vector<double> best_gn(B, INFINITY);
+        std::vector<int> stalled(B, 0);
         for (int it = 0; it < max_newton; ++it) {
             bool any = false;
             for (int64_t b = 0; b < B; ++b) {
@@ -452,6 +457,14 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                     s.status = TK_ENAN;
                 }
                 if (!s.done && o.fixed_iters <= 0 && s.gn <= tol * s.lam * s.an && s.an > 0) s.done = true;
+                if (!s.done && phases == 2 && phase == 0) {
+                    if (s.gn < 0.5 * best_gn[b]) {
+                        best_gn[b] = s.gn;
+                        stalled[b] = 0;
+                    } else if (++stalled[b] >= 3) {
+                        s.done = true;
+                    }
+                }
                 any |= !s.done;
             }
             if (!any) break;
@@ -582,6 +595,13 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
         }
         for (int64_t b = 0; b < B; ++b) {
             ProblemState &s = ps[b];
+            if (phases == 2 && phase == 0) {
+                if (s.status == TK_ENAN) {   // restart the polish from zero
+                    s.status = TK_OK;
+                    TK_HIP_CHECK(hipMemsetAsync(alpha + b * n, 0, n * sizeof(double), st));
+                }
+                continue;
+            }
             if (s.status == TK_OK && o.fixed_iters <= 0 && !(s.gn <= tol * s.lam * s.an)) s.status = TK_ENOCONV;
         }
     }

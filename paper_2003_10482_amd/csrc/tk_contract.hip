@@ -118,35 +118,31 @@ struct In;
 template <int MODE>
 struct In<double, MODE> {
     using R = typename ModeT<MODE>::V;
-    __device__ __forceinline__ static R load(const void *p, int64_t i)
-    {
-        return (R) reinterpret_cast<const double *>(p)[i];
-    }
+    __device__ __forceinline__ static R load(const double *p, int i) { return (R)p[i]; }
 };
 template <int MODE>
 struct In<float, MODE> {
     using R = typename ModeT<MODE>::V;
-    __device__ __forceinline__ static R load(const void *p, int64_t i)
-    {
-        return (R) reinterpret_cast<const float *>(p)[i];
-    }
+    __device__ __forceinline__ static R load(const float *p, int i) { return (R)p[i]; }
 };
 template <int MODE>
 struct In<uint16_t, MODE> {
     using R = typename ModeT<MODE>::V;
-    __device__ __forceinline__ static R load(const void *p, int64_t i)
+    // 16-bit loads are slow in the memory pipeline: load the aligned dword that
+    // holds the value (the packed BF16 buffer is padded to whole dwords) and
+    // take its upper or lower half
+    __device__ __forceinline__ static R load(const uint16_t *p, int i)
     {
-        return (R)bf16_to_float(reinterpret_cast<const uint16_t *>(p)[i]);
+        const uintptr_t a = reinterpret_cast<uintptr_t>(p + i);
+        const uint32_t w = *reinterpret_cast<const uint32_t *>(a & ~(uintptr_t)3);
+        const uint32_t bits = (a & 2) ? (w & 0xffff0000u) : (w << 16);
+        return (R)__uint_as_float(bits);
     }
 };
 template <>
 struct In<DD, ACC_DD> {
     using R = DD;
-    __device__ __forceinline__ static DD load(const void *p, int64_t i)
-    {
-        const double *q = reinterpret_cast<const double *>(p) + 2 * i;
-        return DD{q[0], q[1]};
-    }
+    __device__ __forceinline__ static DD load(const DD *p, int i) { return p[i]; }
 };
 
 // acc += c * v where v may be a DD (intermediate arrays in DD mode).
@@ -176,28 +172,242 @@ __device__ __forceinline__ void acc_unit(double &acc, double c, double z) { acc 
 __device__ __forceinline__ void acc_unit(float &acc, float c, float z) { acc = __builtin_fmaf(c, z, acc); }
 
 // --------------------------------------------------------------- kernel ----
-// Template parameters:
-//   Q     order of the input array (even, >= 2)
-//   NB    column blocks per lane (n <= 64 NB)
-//   TIn   element type of the input array (double, float, uint16_t = BF16, DD)
-//   MODE  accumulation mode
-//   HV    0: values only; 1: tangents of alpha (directional derivative along v);
-//         2: tangents of alpha and of the input array (lower passes of a derivative)
-//   BT    number of alpha vectors handled together (blockIdx.y selects the tile)
-//   RB    rows per transposed-reduction batch
-template <int Q, int NB, typename TIn, int MODE, int HV, int BT, int RB>
-__global__ void __launch_bounds__(256) pair_kernel(PairParams p)
+// Rows are processed in batches that never straddle a 64-column block, so the
+// first block touched (KB) is a compile-time constant inside a batch: the
+// diagonal tie and the lower mask sit in block KB, blocks KB+1.. are full, and
+// the level q-1 update touches block KB only.  Loads address the row through a
+// uniform pointer plus the lane's constant offset.
+
+template <int NB, int KB, int RBMAX>
+constexpr int batch_rows_kb()
 {
-    constexpr bool HVP = HV > 0;
-    constexpr bool ATAN = HV > 1;   // the input array carries a tangent
+    constexpr int segs = NB - KB;
+    constexpr int r0 = 16 / segs;
+    constexpr int r1 = r0 >= 8 ? 8 : r0 >= 4 ? 4 : 2;
+    return r1 > RBMAX ? RBMAX : r1;
+}
+
+template <int Q, int NB, typename TIn, int MODE, int HV, int BT, int RBMAX>
+struct Pass {
+    static constexpr bool HVP = HV > 0;
+    static constexpr bool ATAN = HV > 1;   // the input array carries a tangent
     using V = typename ModeT<MODE>::V;
     using PT = typename ModeT<MODE>::P;
     using CT = typename Coef<MODE>::T;
     using InL = In<TIn, MODE>;
-    using VIn = typename InL::R;               // value type read from the array
-    constexpr int NC = BT * (HVP ? 2 : 1);     // reduced components per row
-    constexpr int LPR = kWave / RB;            // lanes per row in the batch reduction
-    constexpr int QP = Q - 2;                  // unit prefix length
+    using VIn = typename InL::R;
+    static constexpr int NC = BT * (HVP ? 2 : 1);   // reduced components per row
+    static constexpr int QP = Q - 2;                // unit prefix length
+
+    // per-lane registers: column l = 64 b + lane
+    V a_l[BT][NB], v_l[BT][NB];
+    PT U[BT][NB], Ud[BT][NB];        // column sums within the current unit
+    PT unitS[BT], unitSd[BT];        // lane partials of S_{P'}
+    // unit constants (uniform)
+    CT ak0_rr[BT], vk0_rr[BT], cu_tie0[BT], ck_tie0[BT], cud_tie0[BT], vk_tie0[BT];
+    CT inv_rr;
+    int k0, rr;
+    // pointers
+    const TIn *A;
+    const TIn *Ad;
+    const V *alpha_s;
+    const V *vdir_s;
+    PT *buf;      // [RBMAX][NC][64] row partials
+    PT *sbatch;   // [RBMAX][NC] row sums
+    int n, lane;
+
+    __device__ __forceinline__ void begin_unit()
+    {
+#pragma unroll
+        for (int bt = 0; bt < BT; ++bt) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                U[bt][b] = p_zero<PT>();
+                Ud[bt][b] = p_zero<PT>();
+            }
+            unitS[bt] = p_zero<PT>();
+            unitSd[bt] = p_zero<PT>();
+            const V ak = alpha_s[bt * n + k0];
+            ak0_rr[bt] = Coef<MODE>::div(Coef<MODE>::make((double)ak), rr);
+            cu_tie0[bt] = Coef<MODE>::div(ak0_rr[bt], rr + 1);
+            ck_tie0[bt] = Coef<MODE>::div(Coef<MODE>::make((double)ak), rr + 1);
+            if constexpr (HVP) {
+                const V vk = vdir_s[bt * n + k0];
+                vk0_rr[bt] = Coef<MODE>::div(Coef<MODE>::make((double)vk), rr);
+                cud_tie0[bt] = Coef<MODE>::div(vk0_rr[bt], rr + 1);
+                vk_tie0[bt] = Coef<MODE>::div(Coef<MODE>::make((double)vk), rr + 1);
+            }
+        }
+        inv_rr = Coef<MODE>::div(Coef<MODE>::make(1.0), rr);
+    }
+
+    // Rows [k, k + nrows) with k >> 6 == KB; `off` is the packed offset of row k.
+    template <int KB>
+    __device__ __forceinline__ void batch(int &k, int k_hi, int64_t &off)
+    {
+        constexpr int RB = batch_rows_kb<NB, KB, RBMAX>();
+        constexpr int SEG = NB - KB;
+        constexpr int LPR = kWave / RB;
+        const int blk_end = (KB + 1) * kWave;
+        const int lim = blk_end < k_hi ? blk_end : k_hi;
+        const int nrows = (lim - k) < RB ? (lim - k) : RB;
+        const int lane_lo = k - KB * kWave;   // lanes >= lane_lo + r are on or right of the diagonal of row r
+        const bool tail = (n & (kWave - 1)) != 0;
+        const bool lane_in_n = (NB - 1) * kWave + lane < n;
+
+        // ---- phase 1: loads of the batch (row r at offset off + r(n-k) - r(r-1)/2)
+        VIn val[RB][SEG];
+        VIn vald[RB][ATAN ? SEG : 1];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const int64_t roff = off + (int64_t)r * (n - k) - (int64_t)(r * (r - 1) / 2);
+            const TIn *rowp = A + (roff - (k + r));        // rowp[l] is entry (row, l)
+            const TIn *rowd = ATAN ? Ad + (roff - (k + r)) : nullptr;
+#pragma unroll
+            for (int j = 0; j < SEG; ++j) {
+                const int b = KB + j;
+                val[r][j] = zero_like(VIn());
+                if constexpr (ATAN) vald[r][j] = zero_like(VIn());
+                bool ok = r < nrows;
+                if (j == 0) ok = ok && (lane >= lane_lo + r);
+                if (b == NB - 1 && tail) ok = ok && lane_in_n;
+                if (ok) {
+                    val[r][j] = InL::load(rowp, b * kWave + lane);
+                    if constexpr (ATAN) vald[r][j] = InL::load(rowd, b * kWave + lane);
+                }
+            }
+        }
+        // ---- phase 2: in-unit column sums and row partials
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            if (r >= nrows) break;
+            const int kr = k + r;
+            const bool first = (kr == k0);                 // r_{Q-1} = rr only there
+            const bool tie_lane = (lane == lane_lo + r);   // entry l == kr (block KB)
+#pragma unroll
+            for (int bt = 0; bt < BT; ++bt) {
+                const V ak = alpha_s[bt * n + kr];
+                const CT akc = Coef<MODE>::make((double)ak);
+                const CT half_ak = Coef<MODE>::div(akc, 2);
+                const CT cu = first ? ak0_rr[bt] : akc;
+                const CT cu_tie = first ? cu_tie0[bt] : half_ak;
+                const CT ck_tie = first ? ck_tie0[bt] : half_ak;
+                CT cud{}, cud_tie{}, vk_tie{};
+                if constexpr (HVP) {
+                    const V vk = vdir_s[bt * n + kr];
+                    const CT vkc = Coef<MODE>::make((double)vk);
+                    const CT half_vk = Coef<MODE>::div(vkc, 2);
+                    cud = first ? vk0_rr[bt] : vkc;
+                    cud_tie = first ? cud_tie0[bt] : half_vk;
+                    vk_tie = first ? vk_tie0[bt] : half_vk;
+                }
+                PT part = p_zero<PT>(), partd = p_zero<PT>();
+#pragma unroll
+                for (int j = 0; j < SEG; ++j) {
+                    const int b = KB + j;
+                    const VIn x = val[r][j];
+                    if (j == 0) {
+                        const CT cU = tie_lane ? cu_tie : cu;
+                        const CT cP = tie_lane ? ck_tie : Coef<MODE>::make((double)a_l[bt][b]);
+                        acc_cv(U[bt][b], cU, x);
+                        acc_cv(part, cP, x);
+                        if constexpr (HVP) {
+                            const CT cUd = tie_lane ? cud_tie : cud;
+                            const CT cPd = tie_lane ? vk_tie : Coef<MODE>::make((double)v_l[bt][b]);
+                            acc_cv(Ud[bt][b], cUd, x);
+                            acc_cv(partd, cPd, x);
+                            if constexpr (ATAN) {
+                                acc_cv(Ud[bt][b], cU, vald[r][j]);
+                                acc_cv(partd, cP, vald[r][j]);
+                            }
+                        }
+                    } else {
+                        acc_cv(U[bt][b], cu, x);
+                        acc_cv(part, a_l[bt][b], x);
+                        if constexpr (HVP) {
+                            acc_cv(Ud[bt][b], cud, x);
+                            acc_cv(partd, v_l[bt][b], x);
+                            if constexpr (ATAN) {
+                                acc_cv(Ud[bt][b], cu, vald[r][j]);
+                                acc_cv(partd, a_l[bt][b], vald[r][j]);
+                            }
+                        }
+                    }
+                }
+                buf[(r * NC + bt) * kWave + lane] = part;
+                if constexpr (HVP) buf[(r * NC + BT + bt) * kWave + lane] = partd;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        // ---- transposed reduction: lanes [r LPR, (r+1) LPR) sum row r
+        {
+            const int r = lane / LPR, seg = lane % LPR;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                PT s = p_zero<PT>();
+#pragma unroll
+                for (int j = 0; j < RB; ++j) s = p_add(s, buf[(r * NC + c) * kWave + seg * RB + j]);
+#pragma unroll
+                for (int m = 1; m < LPR; m <<= 1) s = p_add(s, p_shfl_xor(s, m));
+                if (seg == 0) sbatch[r * NC + c] = s;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        // ---- level Q-1: S_{P',k}/r_k joins the column sums at index k (block KB),
+        // and S_{P'} += S_k alpha_k / r_k
+        {
+            const int r = lane - lane_lo;
+            if (r >= 0 && r < nrows) {
+                const bool first = (k + r == k0);
+#pragma unroll
+                for (int bt = 0; bt < BT; ++bt) {
+                    const PT s = sbatch[r * NC + bt];
+                    const CT inv = first ? inv_rr : Coef<MODE>::make(1.0);
+                    acc_cv(U[bt][KB], inv, s);
+                    const CT ak = first ? ak0_rr[bt] : Coef<MODE>::make((double)a_l[bt][KB]);
+                    acc_cv(unitS[bt], ak, s);
+                    if constexpr (HVP) {
+                        const PT sd = sbatch[r * NC + BT + bt];
+                        acc_cv(Ud[bt][KB], inv, sd);
+                        const CT vk = first ? vk0_rr[bt] : Coef<MODE>::make((double)v_l[bt][KB]);
+                        acc_cv(unitSd[bt], ak, sd);
+                        acc_cv(unitSd[bt], vk, s);
+                    }
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        off += (int64_t)nrows * (n - k) - (int64_t)(nrows * (nrows - 1) / 2);
+        k += nrows;
+    }
+
+    __device__ __forceinline__ void rows(int k_lo, int k_hi, int64_t off)
+    {
+        int k = k_lo;
+        while (k < k_hi) {
+            const int kb = k >> 6;
+            if (kb == 0) batch<0>(k, k_hi, off);
+            else if constexpr (NB > 1) {
+                if (kb == 1) batch<(NB > 1 ? 1 : 0)>(k, k_hi, off);
+                else if constexpr (NB > 2) {
+                    if (kb == 2) batch<(NB > 2 ? 2 : 0)>(k, k_hi, off);
+                    else if constexpr (NB > 3) batch<(NB > 3 ? 3 : 0)>(k, k_hi, off);
+                }
+            }
+        }
+    }
+};
+
+template <int Q, int NB, typename TIn, int MODE, int HV, int BT, int RBMAX>
+__global__ void __launch_bounds__(256) pair_kernel(PairParams p)
+{
+    using Ps = Pass<Q, NB, TIn, MODE, HV, BT, RBMAX>;
+    using V = typename Ps::V;
+    using PT = typename Ps::PT;
+    using CT = typename Ps::CT;
+    constexpr bool HVP = Ps::HVP;
+    constexpr int NC = Ps::NC;
+    constexpr int QP = Ps::QP;
 
     extern __shared__ __align__(16) unsigned char smem[];
     V *alpha_s = reinterpret_cast<V *>(smem);                 // [BT][n]
@@ -207,59 +417,57 @@ __global__ void __launch_bounds__(256) pair_kernel(PairParams p)
     // the wave index is uniform across the wave: keep it (and all the unit and
     // row bookkeeping derived from it) in scalar registers
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int nw = blockDim.x / kWave;
     size_t stage_bytes = (size_t)BT * n * sizeof(V) * (HVP ? 2 : 1);
     stage_bytes = (stage_bytes + 15) & ~(size_t)15;
-    PT *buf = reinterpret_cast<PT *>(smem + stage_bytes) + (size_t)wid * (RB * NC * kWave + RB * NC);
-    PT *sbatch = buf + RB * NC * kWave;                      // [RB][NC] row sums of a batch
+    PT *wave_base = reinterpret_cast<PT *>(smem + stage_bytes);
+    PT *buf = wave_base + (size_t)wid * (RBMAX * NC * kWave + RBMAX * NC);
+    PT *sbatch = buf + RBMAX * NC * kWave;
     // column sums across units (times the unit multipliers), one slot per lane
-    PT *colw = reinterpret_cast<PT *>(smem + stage_bytes) + (size_t)(blockDim.x / kWave) * (RB * NC * kWave + RB * NC) +
+    PT *colw = wave_base + (size_t)nw * (RBMAX * NC * kWave + RBMAX * NC) +
                (size_t)wid * (BT * NB * kWave * (HVP ? 2 : 1));
     PT *coldw = colw + BT * NB * kWave;
 
     const int b0 = blockIdx.y * BT;      // first alpha vector of this tile
+    Ps ps;
+    ps.n = n;
+    ps.lane = lane;
+    ps.alpha_s = alpha_s;
+    ps.vdir_s = vdir_s;
+    ps.buf = buf;
+    ps.sbatch = sbatch;
     // per-vector arrays (lower passes, BT == 1) sit a_stride entries apart
-    const void *A = p.A;
-    const void *Ad = p.Ad;
-    if (p.a_stride) {
-        const size_t esz = sizeof(TIn);
-        A = reinterpret_cast<const unsigned char *>(p.A) + (size_t)b0 * p.a_stride * esz;
-        if (ATAN) Ad = reinterpret_cast<const unsigned char *>(p.Ad) + (size_t)b0 * p.a_stride * esz;
-    }
+    ps.A = reinterpret_cast<const TIn *>(p.A) + (size_t)b0 * p.a_stride;
+    ps.Ad = Ps::ATAN ? reinterpret_cast<const TIn *>(p.Ad) + (size_t)b0 * p.a_stride : nullptr;
+
     for (int i = threadIdx.x; i < BT * n; i += blockDim.x) {
         const int bt = i / n, j = i - bt * n;
         const bool ok = b0 + bt < p.B;
         alpha_s[i] = ok ? (V)p.alpha[(int64_t)(b0 + bt) * n + j] : V(0);
-        if constexpr (HVP)
-            vdir_s[i] = ok ? (V)p.vdir[(int64_t)(b0 + bt) * n + j] : V(0);
+        if constexpr (HVP) vdir_s[i] = ok ? (V)p.vdir[(int64_t)(b0 + bt) * n + j] : V(0);
     }
     __syncthreads();
-
-    // per-lane column state: l = 64 b + lane
-    V a_l[BT][NB], v_l[BT][NB];
-    PT U[BT][NB], Ud[BT][NB];         // column sums within the current unit
 #pragma unroll
     for (int bt = 0; bt < BT; ++bt)
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const int l = b * kWave + lane;
-            a_l[bt][b] = l < n ? alpha_s[bt * n + l] : V(0);
-            v_l[bt][b] = (HVP && l < n) ? vdir_s[bt * n + l] : V(0);
+            ps.a_l[bt][b] = l < n ? alpha_s[bt * n + l] : V(0);
+            ps.v_l[bt][b] = (HVP && l < n) ? vdir_s[bt * n + l] : V(0);
             colw[(bt * NB + b) * kWave + lane] = p_zero<PT>();
             if constexpr (HVP) coldw[(bt * NB + b) * kWave + lane] = p_zero<PT>();
         }
 
-    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wid;
+    const int64_t wave = (int64_t)blockIdx.x * nw + wid;
     // work plan: wave w owns units (Q >= 4) or rows (Q == 2) [plan[w], plan[w+1]),
     // cut on the host so that every wave gets the same modelled cost
     const int64_t u_lo = p.plan[wave];
     const int64_t u_hi = p.plan[wave + 1];
-    bool active = u_lo < u_hi;
 
-    int P[QP > 0 ? QP : 1];
-    int64_t uidx = u_lo, ustart = 0;
-    int k_first = 0, k_end = n;
     if constexpr (QP > 0) {
-        if (active) {
+        int P[QP];
+        int64_t uidx = u_lo, ustart = 0;
+        if (u_lo < u_hi) {
             unrank_tuple<QP>(u_lo, n, P);
             int tt[Q];
 #pragma unroll
@@ -267,281 +475,107 @@ __global__ void __launch_bounds__(256) pair_kernel(PairParams p)
             tt[QP] = tt[QP + 1] = P[QP - 1];
             ustart = rank_tuple<Q>(tt, n);
         }
-    } else {
-        // Q == 2: one unit, the wave owns rows [u_lo, u_hi); row k starts at k n - k(k-1)/2
-        k_first = (int)u_lo;
-        k_end = (int)u_hi;
-        ustart = (int64_t)k_first * n - (int64_t)k_first * (k_first - 1) / 2;
-    }
-
-    // ---- loop over units
-    while (active) {
-        int k0, rr;
-        CT Cu[BT], Cud[BT];        // unit multiplier (q-1)!/prod r_p(P') alpha^{P'} and its tangent
-        if constexpr (QP > 0) {
-            if (uidx >= u_hi) break;
-            k0 = P[QP - 1];
+        double fq1 = 1.0;
+        for (int i = 2; i <= Q - 1; ++i) fq1 *= (double)i;
+        for (; uidx < u_hi; ++uidx) {
+            // unit multiplier (q-1)!/prod r_p(P') alpha^{P'} and its tangent
+            const int k0 = P[QP - 1];
             int run = 1;
-            double wden = 1.0;
+            int wden = 1;
             for (int i = 1; i < QP; ++i) {
                 run = (P[i] == P[i - 1]) ? run + 1 : 1;
-                wden *= (double)run;
+                wden *= run;
             }
-            rr = run + 1;   // r_{Q-1} of the first row (k == k0)
-            double fq1 = 1.0;
-            for (int i = 2; i <= Q - 1; ++i) fq1 *= (double)i;
+            CT Cu[BT], Cud[BT];
 #pragma unroll
             for (int bt = 0; bt < BT; ++bt) {
-                CT c = Coef<MODE>::div(Coef<MODE>::make(fq1), 1);
+                CT c = Coef<MODE>::make(fq1);
                 CT cd = Coef<MODE>::make(0.0);
                 for (int i = 0; i < QP; ++i) {
-                    const V ai = alpha_s[bt * n + P[i]];
+                    const CT ai = Coef<MODE>::make((double)alpha_s[bt * n + P[i]]);
                     if constexpr (HVP) {
-                        const V vi = vdir_s[bt * n + P[i]];
-                        // (c + eps cd)(ai + eps vi)
-                        cd = Coef<MODE>::mul(cd, Coef<MODE>::make((double)ai));
-                        CT t2 = Coef<MODE>::mul(c, Coef<MODE>::make((double)vi));
-                        if constexpr (MODE == ACC_DD)
-                            cd = dd_add(cd, t2);
-                        else
-                            cd = cd + t2;
+                        const CT vi = Coef<MODE>::make((double)vdir_s[bt * n + P[i]]);
+                        CT t2 = Coef<MODE>::mul(c, vi);
+                        cd = Coef<MODE>::mul(cd, ai);
+                        if constexpr (MODE == ACC_DD) cd = dd_add(cd, t2); else cd = cd + t2;
                     }
-                    c = Coef<MODE>::mul(c, Coef<MODE>::make((double)ai));
+                    c = Coef<MODE>::mul(c, ai);
                 }
-                // divide by the product of run-length factorials (exact integer)
-                Cu[bt] = Coef<MODE>::div(c, (int)wden);
-                Cud[bt] = Coef<MODE>::div(cd, (int)wden);
+                Cu[bt] = Coef<MODE>::div(c, wden);
+                Cud[bt] = Coef<MODE>::div(cd, wden);
             }
-        } else {
-            k0 = 0;
-            rr = 1;
+            ps.k0 = k0;
+            ps.rr = run + 1;
+            ps.begin_unit();
+            ps.rows(k0, n, ustart);
+            // fold the unit into the running column sums
 #pragma unroll
-            for (int bt = 0; bt < BT; ++bt) {
-                Cu[bt] = Coef<MODE>::make(1.0);
-                Cud[bt] = Coef<MODE>::make(0.0);
-            }
-        }
-        const int k_lo = (QP > 0) ? k0 : k_first;
-        const int k_hi = (QP > 0) ? n : k_end;
-        // 1/r, alpha_k0/r and v_k0/r for the unit's first row (r = rr)
-        const CT inv_rr = Coef<MODE>::div(Coef<MODE>::make(1.0), rr);
-        CT ak0_rr[BT], vk0_rr[BT];
-#pragma unroll
-        for (int bt = 0; bt < BT; ++bt) {
-            ak0_rr[bt] = Coef<MODE>::div(Coef<MODE>::make((double)alpha_s[bt * n + k0]), rr);
-            vk0_rr[bt] = HVP ? Coef<MODE>::div(Coef<MODE>::make((double)vdir_s[bt * n + k0]), rr)
-                             : Coef<MODE>::make(0.0);
-        }
-
-#pragma unroll
-        for (int bt = 0; bt < BT; ++bt)
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                U[bt][b] = p_zero<PT>();
-                Ud[bt][b] = p_zero<PT>();
-            }
-        PT unitS[BT], unitSd[BT];   // lane partial of S_{P'}
-#pragma unroll
-        for (int bt = 0; bt < BT; ++bt) {
-            unitS[bt] = p_zero<PT>();
-            unitSd[bt] = p_zero<PT>();
-        }
-
-        int64_t off = ustart;   // offset of row k_lo
-        for (int kb0 = k_lo; kb0 < k_hi; kb0 += RB) {
-            const int nrows = min(RB, k_hi - kb0);
-            // ---- phase 1: issue the loads of the batch
-            VIn val[RB][NB];
-            VIn vald[RB][NB];
-#pragma unroll
-            for (int r = 0; r < RB; ++r) {
-                const int k = kb0 + r;
-                const int64_t roff = off + (int64_t)r * (n - kb0) - (int64_t)r * (r - 1) / 2;
+            for (int bt = 0; bt < BT; ++bt)
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
-                    const int l = b * kWave + lane;
-                    val[r][b] = zero_like(VIn());
-                    vald[r][b] = zero_like(VIn());
-                    if (r < nrows && b >= (k >> 6)) {
-                        if (l >= k && l < n) {
-                            val[r][b] = InL::load(A, roff + (l - k));
-                            if constexpr (ATAN)
-                                vald[r][b] = InL::load(Ad, roff + (l - k));
-                        }
-                    }
-                }
-            }
-            // ---- phase 2: row partials and in-unit column sums.  Only the block
-            // holding the diagonal entry l == k carries the tie factor 1/(r_k+1).
-#pragma unroll
-            for (int r = 0; r < RB; ++r) {
-                if (r >= nrows) break;
-                const int k = kb0 + r;
-                const int kb = k >> 6;
-                const int rk = (QP > 0 && k == k0) ? rr : 1;          // r_{Q-1}(P', k)
-#pragma unroll
-                for (int bt = 0; bt < BT; ++bt) {
-                    const V ak = alpha_s[bt * n + k];
-                    const CT cu = Coef<MODE>::div(Coef<MODE>::make((double)ak), rk);
-                    const CT cu_tie = Coef<MODE>::div(cu, rk + 1);
-                    const CT ck_tie = Coef<MODE>::div(Coef<MODE>::make((double)ak), rk + 1);
-                    CT cud = Coef<MODE>::make(0.0), cud_tie = cud, vk_tie = cud;
+                    PT c = colw[(bt * NB + b) * kWave + lane];
+                    acc_unit(c, Cu[bt], ps.U[bt][b]);
+                    colw[(bt * NB + b) * kWave + lane] = c;
                     if constexpr (HVP) {
-                        const V vk = vdir_s[bt * n + k];
-                        cud = Coef<MODE>::div(Coef<MODE>::make((double)vk), rk);
-                        cud_tie = Coef<MODE>::div(cud, rk + 1);
-                        vk_tie = Coef<MODE>::div(Coef<MODE>::make((double)vk), rk + 1);
-                    }
-                    PT part = p_zero<PT>(), partd = p_zero<PT>();
-#pragma unroll
-                    for (int b = 0; b < NB; ++b) {
-                        if (b < kb) continue;
-                        const int l = b * kWave + lane;
-                        const VIn x = val[r][b];
-                        if (b == kb) {
-                            const bool tie = (l == k);
-                            const CT cU = tie ? cu_tie : cu;
-                            const CT cP = tie ? ck_tie : Coef<MODE>::make((double)a_l[bt][b]);
-                            acc_cv(U[bt][b], cU, x);
-                            acc_cv(part, cP, x);
-                            if constexpr (HVP) {
-                                const VIn xd = vald[r][b];
-                                const CT cUd = tie ? cud_tie : cud;
-                                const CT cPd = tie ? vk_tie : Coef<MODE>::make((double)v_l[bt][b]);
-                                acc_cv(Ud[bt][b], cUd, x);
-                                acc_cv(partd, cPd, x);
-                                if constexpr (ATAN) {
-                                    acc_cv(Ud[bt][b], cU, xd);
-                                    acc_cv(partd, cP, xd);
-                                }
-                            }
-                        } else {
-                            acc_cv(U[bt][b], cu, x);
-                            acc_cv(part, a_l[bt][b], x);
-                            if constexpr (HVP) {
-                                const VIn xd = vald[r][b];
-                                acc_cv(Ud[bt][b], cud, x);
-                                acc_cv(partd, v_l[bt][b], x);
-                                if constexpr (ATAN) {
-                                    acc_cv(Ud[bt][b], cu, xd);
-                                    acc_cv(partd, a_l[bt][b], xd);
-                                }
-                            }
-                        }
-                    }
-                    buf[(r * NC + bt) * kWave + lane] = part;
-                    if constexpr (HVP)
-                        buf[(r * NC + BT + bt) * kWave + lane] = partd;
-                }
-            }
-            __builtin_amdgcn_wave_barrier();
-            // ---- transposed reduction: lanes [r*LPR, (r+1)*LPR) sum row r
-            {
-                const int r = lane / LPR, seg = lane % LPR;
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    PT s = p_zero<PT>();
-#pragma unroll
-                    for (int j = 0; j < RB; ++j)
-                        s = p_add(s, buf[(r * NC + c) * kWave + seg * RB + j]);
-#pragma unroll
-                    for (int m = 1; m < LPR; m <<= 1)
-                        s = p_add(s, p_shfl_xor(s, m));
-                    if (seg == 0)
-                        sbatch[r * NC + c] = s;
-                }
-            }
-            __builtin_amdgcn_wave_barrier();
-            // ---- level Q-1: S_{P',k}/r_k joins the column sums at index k; S_{P'} partial.
-            // r_k = rr only for the unit's first row (k == k0), 1 otherwise.
-            const int bfirst = kb0 >> 6, blast = (kb0 + nrows - 1) >> 6;
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                if (b < bfirst || b > blast) continue;   // blocks holding no row of the batch
-                const int k = b * kWave + lane;
-                if (k >= kb0 && k < kb0 + nrows) {
-                    const int r = k - kb0;
-                    const bool first = (QP > 0) && (k == k0);
-#pragma unroll
-                    for (int bt = 0; bt < BT; ++bt) {
-                        const PT s = sbatch[r * NC + bt];
-                        const CT one = Coef<MODE>::make(1.0);
-                        const CT inv = first ? inv_rr : one;
-                        acc_cv(U[bt][b], inv, s);
-                        // S_{P'} += S_k alpha_k / r_k
-                        const CT ak = first ? ak0_rr[bt] : Coef<MODE>::make((double)a_l[bt][b]);
-                        acc_cv(unitS[bt], ak, s);
-                        if constexpr (HVP) {
-                            const PT sd = sbatch[r * NC + BT + bt];
-                            acc_cv(Ud[bt][b], inv, sd);
-                            const CT vk = first ? vk0_rr[bt] : Coef<MODE>::make((double)v_l[bt][b]);
-                            acc_cv(unitSd[bt], ak, sd);
-                            acc_cv(unitSd[bt], vk, s);
-                        }
+                        PT cd = coldw[(bt * NB + b) * kWave + lane];
+                        acc_unit(cd, Cud[bt], ps.U[bt][b]);
+                        acc_unit(cd, Cu[bt], ps.Ud[bt][b]);
+                        coldw[(bt * NB + b) * kWave + lane] = cd;
                     }
                 }
-            }
-            off += (int64_t)nrows * (n - kb0) - (int64_t)nrows * (nrows - 1) / 2;
-            __builtin_amdgcn_wave_barrier();
-        }
-
-        // ---- unit end: fold the unit into the running column sums
-#pragma unroll
-        for (int bt = 0; bt < BT; ++bt)
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                PT c = colw[(bt * NB + b) * kWave + lane];
-                acc_unit(c, Cu[bt], U[bt][b]);
-                colw[(bt * NB + b) * kWave + lane] = c;
-                if constexpr (HVP) {
-                    PT cd = coldw[(bt * NB + b) * kWave + lane];
-                    acc_unit(cd, Cud[bt], U[bt][b]);
-                    acc_unit(cd, Cu[bt], Ud[bt][b]);
-                    coldw[(bt * NB + b) * kWave + lane] = cd;
-                }
-            }
-        if constexpr (QP > 0) {
             // S_{P'}: wave reduction, written by lane 0
 #pragma unroll
             for (int bt = 0; bt < BT; ++bt) {
-                PT s = unitS[bt];
+                PT s = ps.unitS[bt];
                 for (int m = 1; m < kWave; m <<= 1) s = p_add(s, p_shfl_xor(s, m));
-                PT sd = unitSd[bt];
+                PT sd = ps.unitSd[bt];
                 if constexpr (HVP)
                     for (int m = 1; m < kWave; m <<= 1) sd = p_add(sd, p_shfl_xor(sd, m));
                 if (lane == 0 && b0 + bt < p.B) {
                     store_s(p.S_out, (int64_t)(b0 + bt) * p.units + uidx, s);
-                    if constexpr (HVP)
-                        store_s(p.Sd_out, (int64_t)(b0 + bt) * p.units + uidx, sd);
+                    if constexpr (HVP) store_s(p.Sd_out, (int64_t)(b0 + bt) * p.units + uidx, sd);
                 }
             }
-            // next unit
+            // next unit in nested-loop order
             ustart += (int64_t)(n - k0) * (n - k0 + 1) / 2;
             int pos = QP - 1;
             while (pos >= 0 && P[pos] == n - 1) --pos;
             if (pos < 0) break;
             P[pos] += 1;
             for (int i = pos + 1; i < QP; ++i) P[i] = P[pos];
-            uidx += 1;
-        } else {
-            break;   // Q == 2: the wave's rows are done
+        }
+    } else {
+        // Q == 2: the single unit (empty prefix, multiplier 1); the wave owns rows [u_lo, u_hi)
+        if (u_lo < u_hi) {
+            ps.k0 = 0;
+            ps.rr = 1;
+            ps.begin_unit();
+            const int k_first = (int)u_lo;
+            ps.rows(k_first, (int)u_hi, (int64_t)k_first * n - (int64_t)k_first * (k_first - 1) / 2);
+#pragma unroll
+            for (int bt = 0; bt < BT; ++bt)
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    PT c = colw[(bt * NB + b) * kWave + lane];
+                    c = p_add(c, ps.U[bt][b]);
+                    colw[(bt * NB + b) * kWave + lane] = c;
+                    if constexpr (HVP) coldw[(bt * NB + b) * kWave + lane] = p_add(coldw[(bt * NB + b) * kWave + lane], ps.Ud[bt][b]);
+                }
         }
     }
 
     // ---- workgroup reduction of the column sums, scaled by mu, to partials
     __syncthreads();
-    // the per-wave column sums sit after the batch buffers; gather them into the
-    // (now free) batch-buffer region as [waves][NC][NB*64] and reduce
-    PT *red = reinterpret_cast<PT *>(smem + stage_bytes);
-    const int nw = blockDim.x / kWave;
+    // gather the per-wave column sums into the (now free) batch-buffer region
+    // as [waves][NC][NB*64] and reduce
+    PT *red = wave_base;
 #pragma unroll
     for (int bt = 0; bt < BT; ++bt)
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             red[((size_t)wid * NC + bt) * (NB * kWave) + b * kWave + lane] = colw[(bt * NB + b) * kWave + lane];
             if constexpr (HVP)
-                red[((size_t)wid * NC + BT + bt) * (NB * kWave) + b * kWave + lane] =
-                    coldw[(bt * NB + b) * kWave + lane];
+                red[((size_t)wid * NC + BT + bt) * (NB * kWave) + b * kWave + lane] = coldw[(bt * NB + b) * kWave + lane];
         }
     __syncthreads();
     for (int i = threadIdx.x; i < NC * n; i += blockDim.x) {
@@ -552,8 +586,7 @@ __global__ void __launch_bounds__(256) pair_kernel(PairParams p)
         const bool tan = c >= BT;
         if (b0 + bt >= p.B) continue;
         // partial layout: [vector][workgroup][n] as (hi, lo) pairs
-        double *dst = (tan ? p.part_d : p.part) +
-                      2 * (((int64_t)(b0 + bt) * gridDim.x + blockIdx.x) * n + l);
+        double *dst = (tan ? p.part_d : p.part) + 2 * (((int64_t)(b0 + bt) * gridDim.x + blockIdx.x) * n + l);
         double hi, lo;
         if constexpr (MODE == ACC_DD) {
             // exact scaling by the integer mu: (s.hi + s.lo) * mu as a pair
@@ -621,9 +654,7 @@ constexpr int batch_rows()
     constexpr int NC = BT * (HVP ? 2 : 1);
     constexpr int bytes = NC * kWave * (int)sizeof(PT);
     constexpr int rb0 = 8192 / bytes;
-    constexpr int rb = rb0 >= 8 ? 8 : rb0 >= 4 ? 4 : 2;
-    // the load buffer holds RB x NB values per lane: keep it at <= 16 entries
-    return (rb * NB > 16) ? (16 / NB >= 2 ? 16 / NB : 2) : rb;
+    return rb0 >= 8 ? 8 : rb0 >= 4 ? 4 : 2;   // rows per batch at most (LDS budget)
 }
 
 template <int Q, int NB, typename TIn, int MODE, int HV, int BT>

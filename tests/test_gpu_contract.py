@@ -21,8 +21,9 @@ def _packed_dev(Kh, n, m, dtype="f64"):
     dt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[dtype]
     if dtype == "bf16":
         bits = P.round_bf16(Kh)
-        t = torch.tensor(bits, dtype=torch.float64).to(torch.float32).to(torch.bfloat16)
-        return tk.PackedTensor(t.to(device()), n, m, tk.BF16), bits
+        t = tk.empty_packed(n, m, "bf16", device())
+        t.copy_(torch.tensor(bits, dtype=torch.float64).to(torch.float32).to(torch.bfloat16))
+        return tk.PackedTensor(t, n, m, tk.BF16), bits
     if dtype == "f32":
         r = P.round_fp32(Kh)
         return tk.PackedTensor(torch.tensor(r, dtype=torch.float32, device=device()), n, m, tk.F32), r
