@@ -112,11 +112,13 @@ int tk_contract(const void *d_K, int dtype, int64_t n, int m, const double *d_al
  * gradient map; its Jacobian is symmetric so the VJP equals the JVP):
  *   h_b = (m-1) K x_2 v_b x_3 alpha_b .. x_m alpha_b.
  * If d_g is not NULL it also receives g_b = K . alpha_b^{m-1} from the same
- * pass.  Accumulation: plain FP64 for TK_F64 storage, FP32 otherwise.
+ * pass.  `acc`: TK_ACC_AUTO and TK_ACC_F64 = plain FP64 for TK_F64 storage
+ * (FP32 for FP32/BF16 storage); TK_ACC_COMPENSATED = compensated FP64
+ * (TK_F64 storage only).
  * Errors: as tk_contract.
  */
 int tk_hvp(const void *d_K, int dtype, int64_t n, int m, const double *d_alpha,
-           const double *d_v, int64_t B, double *d_h, double *d_g, void *d_work,
+           const double *d_v, int64_t B, double *d_h, double *d_g, int acc, void *d_work,
            size_t work_bytes, void *stream);
 
 /* Options of the dual solve (host struct). */

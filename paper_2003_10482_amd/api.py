@@ -115,7 +115,7 @@ def contract(K: PackedTensor, alpha: torch.Tensor, acc: int = ACC_AUTO,
 
 
 def hvp(K: PackedTensor, alpha: torch.Tensor, v: torch.Tensor, with_g: bool = False,
-        work: Optional[torch.Tensor] = None):
+        work: Optional[torch.Tensor] = None, acc: int = ACC_AUTO):
     """h = (m-1) K x_2 v x_3 alpha .. x_m alpha (and g when with_g)."""
     alpha = _dev_f64(alpha, "alpha")
     v = _dev_f64(v, "v")
@@ -129,7 +129,7 @@ def hvp(K: PackedTensor, alpha: torch.Tensor, v: torch.Tensor, with_g: bool = Fa
     if work is None:
         work = _workspace(contract_workspace(K.n, K.m, B, K.dtype), alpha.device)
     _lib.check(_lib.load().tk_hvp(_ptr(K.data), K.dtype, K.n, K.m, _ptr(a2), _ptr(v2), B, _ptr(h), _ptr(g),
-                                  _ptr(work), work.numel(), _stream()))
+                                  acc, _ptr(work), work.numel(), _stream()))
     if with_g:
         return h.reshape(alpha.shape), g.reshape(alpha.shape)
     return h.reshape(alpha.shape)

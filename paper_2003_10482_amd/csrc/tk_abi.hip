@@ -94,7 +94,8 @@ ContractPlan make_plan(int64_t n, int m, int64_t B, int mode, bool hv)
 int mode_for(int dtype, int acc, bool hv, int *mode)
 {
     if (dtype == TK_F64) {
-        if (hv) { *mode = ACC_PLAIN64; return TK_OK; }
+        if (hv && acc == TK_ACC_COMPENSATED) { *mode = ACC_DD; return TK_OK; }
+        if (hv && (acc == TK_ACC_AUTO || acc == TK_ACC_F64)) { *mode = ACC_PLAIN64; return TK_OK; }
         if (acc == TK_ACC_AUTO || acc == TK_ACC_COMPENSATED) { *mode = ACC_DD; return TK_OK; }
         if (acc == TK_ACC_F64) { *mode = ACC_PLAIN64; return TK_OK; }
         return fail(TK_EINVAL, "accumulation %d not available for FP64 storage", acc);
@@ -195,7 +196,7 @@ int run_contract(const void *K, int dtype, int64_t n, int m, const double *alpha
 
 size_t contract_ws(int64_t n, int m, int64_t B, int dtype)
 {
-    size_t a = make_plan(n, m, B, dtype == TK_F64 ? ACC_DD : ACC_PLAIN32, false).bytes;
+    size_t a = make_plan(n, m, B, dtype == TK_F64 ? ACC_DD : ACC_PLAIN32, true).bytes;
     size_t b = make_plan(n, m, B, dtype == TK_F64 ? ACC_PLAIN64 : ACC_PLAIN32, true).bytes;
     return a > b ? a : b;
 }
@@ -280,7 +281,7 @@ int tk_contract(const void *d_K, int dtype, int64_t n, int m, const double *d_al
 }
 
 int tk_hvp(const void *d_K, int dtype, int64_t n, int m, const double *d_alpha, const double *d_v, int64_t B,
-           double *d_h, double *d_g, void *d_work, size_t work_bytes, void *stream)
+           double *d_h, double *d_g, int acc, void *d_work, size_t work_bytes, void *stream)
 {
     int rc;
     if ((rc = check_nm(n, m))) return rc;
@@ -288,7 +289,7 @@ int tk_hvp(const void *d_K, int dtype, int64_t n, int m, const double *d_alpha, 
     if (B < 1 || B > 65535) return fail(TK_EINVAL, "B must be in [1, 65535]");
     if (!d_K || !d_alpha || !d_v || !d_h) return fail(TK_EINVAL, "null device pointer");
     int mode;
-    if ((rc = mode_for(dtype, TK_ACC_AUTO, true, &mode))) return rc;
+    if ((rc = mode_for(dtype, acc, true, &mode))) return rc;
     return run_contract(d_K, dtype, n, m, d_alpha, d_v, B, d_g, d_h, mode, d_work, work_bytes, as_stream(stream));
 }
 
@@ -817,8 +818,10 @@ int tk_dmse_dlambda(const void *d_K, int dtype, int64_t n, int m, const double *
     const int maxit = max_cg > 0 ? max_cg : 5000;
     const double tol = cg_tol > 0 ? cg_tol : 1e-12;
     for (int j = 0; j < maxit && std::sqrt(rr) > tol * r0 && rr > 0; ++j) {
+        // compensated directional derivatives on FP64 storage: at the dual
+        // optimum the products cancel heavily and CG amplifies their error
         if ((rc = run_contract(d_K, dtype, n, m, d_alpha, dv, 1, nullptr, hd,
-                               dtype == TK_F64 ? ACC_PLAIN64 : ACC_PLAIN32, cw, cw_bytes, st)))
+                               dtype == TK_F64 ? ACC_DD : ACC_PLAIN32, cw, cw_bytes, st)))
             return rc;
         TK_CHK(vec_shift_dot(dv, hd, lamc, sc, 1, n, st));
         double dhd;

@@ -825,9 +825,16 @@ hipError_t launch_pass(int q, int in_kind, int mode, int hv, int bt, const PairP
     // in_kind: 0 double, 1 float, 2 bf16, 3 DD intermediate;
     // hv: 0 value only, 1 tangent of alpha, 2 tangent of alpha and of the array
     if (mode == ACC_DD) {
-        if (hv) return hipErrorInvalidValue;
-        if (in_kind == 0) return dispatch_q<double, ACC_DD, 0>(q, pp, groups, bt, st);
-        if (in_kind == 3) return dispatch_q<DD, ACC_DD, 0>(q, pp, groups, bt, st);
+        if (in_kind == 0) {
+            if (hv == 0) return dispatch_q<double, ACC_DD, 0>(q, pp, groups, bt, st);
+            if (hv == 1) return dispatch_q<double, ACC_DD, 1>(q, pp, groups, bt, st);
+            return hipErrorInvalidValue;
+        }
+        if (in_kind == 3) {
+            if (hv == 0) return dispatch_q<DD, ACC_DD, 0>(q, pp, groups, bt, st);
+            if (hv == 2) return dispatch_q<DD, ACC_DD, 2>(q, pp, groups, bt, st);
+            return hipErrorInvalidValue;
+        }
         return hipErrorInvalidValue;
     }
     if (mode == ACC_PLAIN64) {
