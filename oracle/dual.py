@@ -113,6 +113,43 @@ def solve_linear(X, y, lam: float, m: int, **kw):
     return solve_dual_newton(c, j, y, lam, m, **kw)
 
 
+def dual_grad_exact_linear(X, y, lam: float, m: int, alpha) -> np.ndarray:
+    """Gradient X (X^T alpha)^{m-1} + lam alpha - y of the dual objective of the
+    linear tensor kernel (Section 3.2, closed form of K . alpha^{m-1}), evaluated
+    in exact rational arithmetic on the given FP64 values and rounded once.
+
+    Near the optimum the terms cancel by many orders of magnitude, so a plain
+    FP64 evaluation loses most of its digits; this one does not.  Small
+    problems only (cost grows with n d and the operand bit lengths)."""
+    from fractions import Fraction
+    X = np.asarray(X, dtype=np.float64)
+    n, d = X.shape
+    Xf = [[Fraction(float(v)) for v in row] for row in X]
+    af = [Fraction(float(v)) for v in np.asarray(alpha, dtype=np.float64)]
+    u = [sum((Xf[i][j] * af[i] for i in range(n)), Fraction(0)) for j in range(d)]
+    w = [uj ** (m - 1) for uj in u]
+    lf = Fraction(float(lam))
+    yf = [Fraction(float(v)) for v in np.asarray(y, dtype=np.float64)]
+    g = [sum((Xf[i][j] * w[j] for j in range(d)), Fraction(0)) + lf * af[i] - yf[i] for i in range(n)]
+    return np.array([float(gi) for gi in g])
+
+
+def refine_linear_exact(X, y, lam: float, m: int, alpha, steps: int = 2) -> np.ndarray:
+    """Newton corrections alpha <- alpha - H^{-1} g with the gradient g taken
+    exactly (dual_grad_exact_linear) and H = (m-1) X diag(u^{m-2}) X^T + lam I
+    in FP64: the correction is tiny, so its own rounding does not matter, and
+    the result is the FP64 point nearest (to within a few units in the last
+    place times the condition number) to the exact optimum."""
+    X = np.asarray(X, dtype=np.float64)
+    a = np.array(alpha, dtype=np.float64)
+    for _ in range(steps):
+        g = dual_grad_exact_linear(X, y, lam, m, a)
+        u = X.T @ a
+        H = (m - 1) * (X * (u ** (m - 2))) @ X.T + lam * np.eye(a.size)
+        a = a - sla.solve(H, g, assume_a="pos")
+    return a
+
+
 def solve_path(X, y, lambdas, m: int, **kw):
     """Independent solves along a lambda path, warm-started in increasing
     lambda order (the minimiser of each is unique, so warm starts only change

@@ -70,16 +70,30 @@ struct ContractPlan {
 
 size_t inter_size(int mode) { return mode == ACC_DD ? 16 : mode == ACC_PLAIN64 ? 8 : 4; }
 
-ContractPlan make_plan(int64_t n, int m, int64_t B, int mode, bool hv)
+// Kernel selection of pass i (first pass reads the stored tensor, later ones
+// the intermediate arrays): input kind, tangent kind and vector tile.
+int pass_in_kind(int i, int dtype, int mode)
+{
+    if (i == 0) return dtype == TK_F64 ? 0 : dtype == TK_F32 ? 1 : 2;
+    return mode == ACC_DD ? 3 : mode == ACC_PLAIN64 ? 0 : 1;
+}
+int pass_hv(int i, bool hv) { return hv ? (i == 0 ? 1 : 2) : 0; }
+int pass_bt(int i, int mode, int64_t B) { return (i == 0 && mode == ACC_PLAIN32 && B >= 4) ? 4 : 1; }
+
+ContractPlan make_plan(int64_t n, int m, int64_t B, int mode, bool hv, int dtype)
 {
     ContractPlan pl;
     size_t off = 0;
     for (int q = m; q >= 2; q -= 2) {
+        const int i = pl.npass;
         PassPlan &p = pl.pass[pl.npass++];
         p.q = q;
         p.count = packed_count(n, q);
         p.units = q >= 4 ? packed_count(n, q - 2) : 1;
-        p.groups = pass_groups(q, n, p.count);
+        p.groups = pass_groups(q, n, p.count,
+                               q >= 4 ? pass_resident(q, pass_in_kind(i, dtype, mode), mode, pass_hv(i, hv),
+                                                      pass_bt(i, mode, B), n)
+                                      : 1);
         p.s_bytes = q >= 4 ? align256((size_t)B * p.units * inter_size(mode)) : 0;
         p.s_off = off;
         off += p.s_bytes * (hv ? 2 : 1);
@@ -119,13 +133,13 @@ int run_contract(const void *K, int dtype, int64_t n, int m, const double *alpha
                  int64_t B, double *g, double *h, int mode, void *work, size_t work_bytes, hipStream_t st)
 {
     const bool hv = vdir != nullptr;
-    const ContractPlan pl = make_plan(n, m, B, mode, hv);
+    const ContractPlan pl = make_plan(n, m, B, mode, hv, dtype);
     if (work_bytes < pl.bytes || (pl.bytes && !work))
         return fail(TK_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", work_bytes, pl.bytes);
     unsigned char *w = reinterpret_cast<unsigned char *>(work);
     const void *A = K;
     const void *Ad = nullptr;
-    int in_kind = dtype == TK_F64 ? 0 : dtype == TK_F32 ? 1 : 2;
+    int in_kind = pass_in_kind(0, dtype, mode);
     int64_t a_stride = 0;
     double mu = 1.0;
     ReduceParams rv{}, rt{};
@@ -149,8 +163,8 @@ int run_contract(const void *K, int dtype, int64_t n, int m, const double *alpha
         int perr = 0;
         prm.plan = pass_plan(pp.q, n, pp.groups, &perr);
         if (perr || !prm.plan) return fail(TK_EHIP, "could not place the work plan of pass q=%d", pp.q);
-        const int hvl = hv ? (i == 0 ? 1 : 2) : 0;
-        const int bt = (i == 0 && mode == ACC_PLAIN32 && B >= 4) ? 4 : 1;
+        const int hvl = pass_hv(i, hv);
+        const int bt = pass_bt(i, mode, B);
         TimedLaunch tl{};
         bool timed = false;
         if (i == 0) {
@@ -176,7 +190,7 @@ int run_contract(const void *K, int dtype, int64_t n, int m, const double *alpha
         A = prm.S_out;
         Ad = prm.Sd_out;
         a_stride = pp.units;
-        in_kind = mode == ACC_DD ? 3 : mode == ACC_PLAIN64 ? 0 : 1;
+        in_kind = pass_in_kind(i + 1, dtype, mode);
         mu *= (double)(pp.q - 1) * (double)(pp.q - 2);
     }
     rv.npass = rt.npass = pl.npass;
@@ -196,9 +210,16 @@ int run_contract(const void *K, int dtype, int64_t n, int m, const double *alpha
 
 size_t contract_ws(int64_t n, int m, int64_t B, int dtype)
 {
-    size_t a = make_plan(n, m, B, dtype == TK_F64 ? ACC_DD : ACC_PLAIN32, true).bytes;
-    size_t b = make_plan(n, m, B, dtype == TK_F64 ? ACC_PLAIN64 : ACC_PLAIN32, true).bytes;
-    return a > b ? a : b;
+    // every accumulation mode and both the value and the derivative pass can
+    // run in one workspace; grids follow each kernel's occupancy
+    size_t w = 0;
+    const int modes[2] = {dtype == TK_F64 ? ACC_DD : ACC_PLAIN32, dtype == TK_F64 ? ACC_PLAIN64 : ACC_PLAIN32};
+    for (int mode : modes)
+        for (int hv = 0; hv < 2; ++hv) {
+            const size_t b = make_plan(n, m, B, mode, hv != 0, dtype).bytes;
+            if (b > w) w = b;
+        }
+    return w;
 }
 
 }  // namespace

@@ -115,23 +115,51 @@ __device__ __forceinline__ double p_value(float a) { return (double)a; }
 // Load one entry of an input array as the value type (+ low part for DD arrays).
 template <typename TIn, int MODE>
 struct In;
+// Buffer-resource loads: a byte offset past the descriptor's range (or a
+// negative one, which wraps) reads 0 instead of faulting, so rows past a batch
+// and lanes left of the diagonal need no address clamping or branches.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ Rsrc make_rsrc(const void *base, int64_t bytes)
+{
+    const int64_t cap = 0xffffffffLL;
+    const uint32_t nr = (uint32_t)(bytes < 0 ? 0 : (bytes > cap ? cap : bytes));
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)nr, 0x00020000);
+}
+
 template <int MODE>
 struct In<double, MODE> {
     using R = typename ModeT<MODE>::V;
-    __device__ __forceinline__ static R load(const double *p, int i) { return (R)p[i]; }
+    static constexpr int kSize = 8;
+    __device__ __forceinline__ static R load(const double *p, uint32_t i) { return (R)p[i]; }
+    __device__ __forceinline__ static R load_buf(Rsrc rs, uint32_t byte_off)
+    {
+        return (R)__builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, byte_off, 0, 0));
+    }
 };
 template <int MODE>
 struct In<float, MODE> {
     using R = typename ModeT<MODE>::V;
-    __device__ __forceinline__ static R load(const float *p, int i) { return (R)p[i]; }
+    static constexpr int kSize = 4;
+    __device__ __forceinline__ static R load(const float *p, uint32_t i) { return (R)p[i]; }
+    __device__ __forceinline__ static R load_buf(Rsrc rs, uint32_t byte_off)
+    {
+        return (R)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, byte_off, 0, 0));
+    }
 };
 template <int MODE>
 struct In<uint16_t, MODE> {
     using R = typename ModeT<MODE>::V;
+    static constexpr int kSize = 2;
+    __device__ __forceinline__ static R load_buf(Rsrc rs, uint32_t byte_off)
+    {
+        const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(rs, byte_off & ~3u, 0, 0);
+        const uint32_t bits = (byte_off & 2u) ? (w & 0xffff0000u) : (w << 16);
+        return (R)__uint_as_float(bits);
+    }
     // 16-bit loads are slow in the memory pipeline: load the aligned dword that
     // holds the value (the packed BF16 buffer is padded to whole dwords) and
     // take its upper or lower half
-    __device__ __forceinline__ static R load(const uint16_t *p, int i)
+    __device__ __forceinline__ static R load(const uint16_t *p, uint32_t i)
     {
         const uintptr_t a = reinterpret_cast<uintptr_t>(p + i);
         const uint32_t w = *reinterpret_cast<const uint32_t *>(a & ~(uintptr_t)3);
@@ -142,12 +170,28 @@ struct In<uint16_t, MODE> {
 template <>
 struct In<DD, ACC_DD> {
     using R = DD;
-    __device__ __forceinline__ static DD load(const DD *p, int i) { return p[i]; }
+    static constexpr int kSize = 16;
+    __device__ __forceinline__ static DD load(const DD *p, uint32_t i) { return p[i]; }
+    __device__ __forceinline__ static DD load_buf(Rsrc rs, uint32_t byte_off)
+    {
+        return __builtin_bit_cast(DD, __builtin_amdgcn_raw_buffer_load_b128(rs, byte_off, 0, 0));
+    }
 };
 
 // acc += c * v where v may be a DD (intermediate arrays in DD mode).
 template <typename PT, typename CT, typename VT>
 __device__ __forceinline__ void acc_cv(PT &acc, CT c, VT v) { acc_fma(acc, c, v); }
+
+// Entry weight on the block of the diagonal: d = column - row.  Left of the
+// diagonal (d < 0) the lane holds another row's entry; on it (a tie between
+// the last two indices) every coefficient of the entry is halved, exactly.
+__device__ __forceinline__ double tie_scale(int d, double x) { return d < 0 ? 0.0 : (d == 0 ? 0.5 * x : x); }
+__device__ __forceinline__ float tie_scale(int d, float x) { return d < 0 ? 0.0f : (d == 0 ? 0.5f * x : x); }
+__device__ __forceinline__ DD tie_scale(int d, DD x)
+{
+    const double f = d < 0 ? 0.0 : (d == 0 ? 0.5 : 1.0);
+    return DD{f * x.hi, f * x.lo};
+}
 
 __device__ __forceinline__ DD zero_like(DD) { return DD{0.0, 0.0}; }
 __device__ __forceinline__ double zero_like(double) { return 0.0; }
@@ -210,11 +254,32 @@ struct Pass {
     // pointers
     const TIn *A;
     const TIn *Ad;
+    Rsrc rs, rsd;      // descriptors of A and Ad from the wave's first entry e_base on
+    int64_t e_base;
     const V *alpha_s;
     const V *vdir_s;
     PT *buf;      // [RBMAX][NC][64] row partials
     PT *sbatch;   // [RBMAX][NC] row sums
     int n, lane;
+
+    // Descriptors for the wave's entries from e0 on (16-byte aligned base, so
+    // BF16 dword loads stay aligned); count entries per input array.
+    int32_t dshift;   // byte shift of the tangent array's descriptor
+    __device__ __forceinline__ void set_base(int64_t e0, int64_t count)
+    {
+        constexpr int64_t ES = InL::kSize;
+        const int64_t end_bytes = (count * ES + 3) & ~(int64_t)3;
+        const uintptr_t a0 = reinterpret_cast<uintptr_t>(A + e0) & ~(uintptr_t)15;
+        e_base = e0 - (int64_t)(reinterpret_cast<uintptr_t>(A + e0) - a0) / ES;
+        rs = make_rsrc(reinterpret_cast<const void *>(a0), end_bytes - e_base * ES);
+        dshift = 0;
+        if constexpr (ATAN) {
+            const uintptr_t d0 = reinterpret_cast<uintptr_t>(Ad + e0) & ~(uintptr_t)15;
+            const int64_t eb_d = e0 - (int64_t)(reinterpret_cast<uintptr_t>(Ad + e0) - d0) / ES;
+            rsd = make_rsrc(reinterpret_cast<const void *>(d0), end_bytes - eb_d * ES);
+            dshift = (int32_t)((e_base - eb_d) * ES);
+        }
+    }
 
     __device__ __forceinline__ void begin_unit()
     {
@@ -381,17 +446,145 @@ struct Pass {
         k += nrows;
     }
 
+    // Rows [k, k + nrows) with k >> 6 == KB, none of them the first row of a
+    // unit with a run multiplicity (their coefficients are the plain alpha_k,
+    // halved on the diagonal).  No divergent branches around the loads.
+    template <int KB>
+    __device__ __forceinline__ void batch_fast(int &k, int k_hi, int64_t &off)
+    {
+        constexpr int RB = batch_rows_kb<NB, KB, RBMAX>();
+        constexpr int SEG = NB - KB;
+        constexpr int LPR = kWave / RB;
+        const int blk_end = (KB + 1) * kWave;
+        const int lim = blk_end < k_hi ? blk_end : k_hi;
+        const int nrows = (lim - k) < RB ? (lim - k) : RB;
+        const int lane_lo = k - KB * kWave;
+
+        // ---- phase 1: every lane loads every segment of every row through the
+        // buffer descriptor.  Left of the diagonal the lane reads another row's
+        // entry (zeroed in phase 2); columns past n read finite entries or zeros
+        // (their alpha and v are 0).
+        VIn val[RB][SEG];
+        VIn vald[RB][ATAN ? SEG : 1];
+        constexpr uint32_t ES = (uint32_t)InL::kSize;
+        // byte offset (from the descriptor base) of entry (row, column KB*64) of
+        // row r; rows past the batch follow the same recurrence and read either
+        // real entries or zeros (their row coefficients are zero below)
+        uint32_t so = (uint32_t)((off - k - e_base + KB * kWave) * (int64_t)ES);
+        const uint32_t vlane = (uint32_t)lane * ES;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const uint32_t vo = so + vlane;
+#pragma unroll
+            for (int j = 0; j < SEG; ++j) {
+                val[r][j] = InL::load_buf(rs, vo + (uint32_t)(j * kWave) * ES);
+                if constexpr (ATAN) vald[r][j] = InL::load_buf(rsd, vo + (uint32_t)dshift + (uint32_t)(j * kWave) * ES);
+            }
+            so += (uint32_t)(n - k - 1 - r) * ES;
+        }
+        // ---- phase 2: in-unit column sums and row partials.  Rows past the
+        // batch run with zero row coefficients (their row partials are never
+        // read), so the loads above are not tied to per-row branches.
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const bool live = r < nrows;
+            const int kr = live ? k + r : k;
+            const int d = lane - (lane_lo + r);
+#pragma unroll
+            for (int bt = 0; bt < BT; ++bt) {
+                const V ak_r = alpha_s[bt * n + kr];
+                const V ak = live ? ak_r : V(0);
+                V vk{};
+                if constexpr (HVP) {
+                    const V vk_r = vdir_s[bt * n + kr];
+                    vk = live ? vk_r : V(0);
+                }
+                PT part = p_zero<PT>(), partd = p_zero<PT>();
+#pragma unroll
+                for (int j = 0; j < SEG; ++j) {
+                    const int b = KB + j;
+                    VIn x = val[r][j];
+                    if (j == 0) x = tie_scale(d, x);
+                    acc_cv(U[bt][b], ak, x);
+                    acc_cv(part, a_l[bt][b], x);
+                    if constexpr (HVP) {
+                        acc_cv(Ud[bt][b], vk, x);
+                        acc_cv(partd, v_l[bt][b], x);
+                        if constexpr (ATAN) {
+                            VIn xd = vald[r][j];
+                            if (j == 0) xd = tie_scale(d, xd);
+                            acc_cv(Ud[bt][b], ak, xd);
+                            acc_cv(partd, a_l[bt][b], xd);
+                        }
+                    }
+                }
+                buf[(r * NC + bt) * kWave + lane] = part;
+                if constexpr (HVP) buf[(r * NC + BT + bt) * kWave + lane] = partd;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        // ---- transposed reduction: lanes [r LPR, (r+1) LPR) sum row r
+        {
+            const int r = lane / LPR, seg = lane % LPR;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                PT s = p_zero<PT>();
+#pragma unroll
+                for (int j = 0; j < RB; ++j) s = p_add(s, buf[(r * NC + c) * kWave + seg * RB + j]);
+#pragma unroll
+                for (int m = 1; m < LPR; m <<= 1) s = p_add(s, p_shfl_xor(s, m));
+                if (seg == 0) sbatch[r * NC + c] = s;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        // ---- level Q-1: S_{P',k} joins the column sums at index k (block KB),
+        // and S_{P'} += S_k alpha_k
+        {
+            const int r = lane - lane_lo;
+            if (r >= 0 && r < nrows) {
+#pragma unroll
+                for (int bt = 0; bt < BT; ++bt) {
+                    const PT s = sbatch[r * NC + bt];
+                    U[bt][KB] = p_add(U[bt][KB], s);
+                    acc_cv(unitS[bt], a_l[bt][KB], s);
+                    if constexpr (HVP) {
+                        const PT sd = sbatch[r * NC + BT + bt];
+                        Ud[bt][KB] = p_add(Ud[bt][KB], sd);
+                        acc_cv(unitSd[bt], a_l[bt][KB], sd);
+                        acc_cv(unitSd[bt], v_l[bt][KB], s);
+                    }
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        off += (int64_t)nrows * (n - k) - (int64_t)(nrows * (nrows - 1) / 2);
+        k += nrows;
+    }
+
     __device__ __forceinline__ void rows(int k_lo, int k_hi, int64_t off)
     {
         int k = k_lo;
+        // the first row of a unit repeats the prefix's last index (run rr):
+        // general coefficients, one row
+        if (rr > 1 && k == k0 && k < k_hi) {
+            const int kb = k >> 6;
+            if (kb == 0) batch<0>(k, k + 1, off);
+            else if constexpr (NB > 1) {
+                if (kb == 1) batch<(NB > 1 ? 1 : 0)>(k, k + 1, off);
+                else if constexpr (NB > 2) {
+                    if (kb == 2) batch<(NB > 2 ? 2 : 0)>(k, k + 1, off);
+                    else if constexpr (NB > 3) batch<(NB > 3 ? 3 : 0)>(k, k + 1, off);
+                }
+            }
+        }
         while (k < k_hi) {
             const int kb = k >> 6;
-            if (kb == 0) batch<0>(k, k_hi, off);
+            if (kb == 0) batch_fast<0>(k, k_hi, off);
             else if constexpr (NB > 1) {
-                if (kb == 1) batch<(NB > 1 ? 1 : 0)>(k, k_hi, off);
+                if (kb == 1) batch_fast<(NB > 1 ? 1 : 0)>(k, k_hi, off);
                 else if constexpr (NB > 2) {
-                    if (kb == 2) batch<(NB > 2 ? 2 : 0)>(k, k_hi, off);
-                    else if constexpr (NB > 3) batch<(NB > 3 ? 3 : 0)>(k, k_hi, off);
+                    if (kb == 2) batch_fast<(NB > 2 ? 2 : 0)>(k, k_hi, off);
+                    else if constexpr (NB > 3) batch_fast<(NB > 3 ? 3 : 0)>(k, k_hi, off);
                 }
             }
         }
@@ -474,6 +667,7 @@ __global__ void __launch_bounds__(256) pair_kernel(PairParams p)
             for (int i = 0; i < QP; ++i) tt[i] = P[i];
             tt[QP] = tt[QP + 1] = P[QP - 1];
             ustart = rank_tuple<Q>(tt, n);
+            ps.set_base(ustart, p.count);
         }
         double fq1 = 1.0;
         for (int i = 2; i <= Q - 1; ++i) fq1 *= (double)i;
@@ -551,7 +745,9 @@ __global__ void __launch_bounds__(256) pair_kernel(PairParams p)
             ps.rr = 1;
             ps.begin_unit();
             const int k_first = (int)u_lo;
-            ps.rows(k_first, (int)u_hi, (int64_t)k_first * n - (int64_t)k_first * (k_first - 1) / 2);
+            const int64_t off0 = (int64_t)k_first * n - (int64_t)k_first * (k_first - 1) / 2;
+            ps.set_base(off0, p.count);
+            ps.rows(k_first, (int)u_hi, off0);
 #pragma unroll
             for (int bt = 0; bt < BT; ++bt)
 #pragma unroll
@@ -677,6 +873,12 @@ hipError_t launch_pair(const PairParams &pp, int groups, int btiles, hipStream_t
         hipError_t e = hipFuncSetAttribute((const void *)kern,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
+    }
+    if (pp.occ_query) {
+        int nb = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, 256, lds);
+        *pp.occ_query = nb;
+        return e;
     }
     hipLaunchKernelGGL(kern, dim3(groups, btiles), dim3(256), lds, st, pp);
     return hipGetLastError();
@@ -806,17 +1008,47 @@ const int64_t *pass_plan(int q, int64_t n, int groups, int *err)
 }
 
 // Number of workgroups of one pass over an order-q array of `count` entries.
-int pass_groups(int q, int64_t n, int64_t count)
+int pass_groups(int q, int64_t n, int64_t count, int resident)
 {
     if (q == 2) {   // waves split the rows of the single unit: a few rows per wave
         int64_t g = (n + 15) / 16;
         return (int)(g < 1 ? 1 : g);
     }
-    // about 4K entries per wave, at most 3 resident workgroups per CU on 256 CUs
+    // at least about 4K entries per wave; at most one resident wave slot each
     int64_t g = (count + 4 * 4096 - 1) / (4 * 4096);
     if (g < 1) g = 1;
-    if (g > 768) g = 768;
+    if (g > resident) g = resident;
     return (int)g;
+}
+
+namespace {
+std::mutex g_occ_mu;
+std::map<std::tuple<int, int, int, int, int, int, int>, int> g_occ;
+}  // namespace
+
+int pass_resident(int q, int in_kind, int mode, int hv, int bt, int64_t n)
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    const int nb = (int)((n + kWave - 1) / kWave);
+    const auto key = std::make_tuple(dev, q, in_kind, mode, hv, bt, nb);
+    {
+        std::lock_guard<std::mutex> lk(g_occ_mu);
+        auto it = g_occ.find(key);
+        if (it != g_occ.end()) return it->second;
+    }
+    PairParams pp{};
+    int per_cu = 0;
+    pp.n = (int)n;
+    pp.B = bt;
+    pp.occ_query = &per_cu;
+    if (launch_pass(q, in_kind, mode, hv, bt, pp, 1, nullptr) != hipSuccess || per_cu <= 0) per_cu = 1;
+    const int r = per_cu * cus;
+    std::lock_guard<std::mutex> lk(g_occ_mu);
+    g_occ[key] = r;
+    return r;
 }
 
 hipError_t launch_pass(int q, int in_kind, int mode, int hv, int bt, const PairParams &pp,

@@ -24,6 +24,8 @@ struct PairParams {
     double *part;        // [B][groups][n] (hi, lo) column-sum partials, already scaled by mu
     double *part_d;      // tangent partials
     const int64_t *plan; // [waves + 1] first unit (q >= 4) or row (q == 2) of every wave
+    int *occ_query;      // host only: when set, the launcher stores the resident workgroups per CU
+                         // of the selected kernel here instead of launching it
 };
 
 constexpr int kMaxPasses = kMaxOrder / 2;
@@ -36,7 +38,11 @@ struct ReduceParams {
     double *out;          // [B][n]
 };
 
-int pass_groups(int q, int64_t n, int64_t count);
+// Resident workgroups per CU of the kernel that launch_pass selects (cached).
+int pass_resident(int q, int in_kind, int mode, int hv, int bt, int64_t n);
+// Workgroups of one pass: enough to fill every CU to the kernel's occupancy
+// (one wave of persistent work each), fewer for small arrays.
+int pass_groups(int q, int64_t n, int64_t count, int resident);
 // Device copy of the balanced work plan of one pass (cached per (n, q, groups)).
 const int64_t *pass_plan(int q, int64_t n, int groups, int *err);
 hipError_t launch_pass(int q, int in_kind, int mode, int hv, int bt, const PairParams &pp,

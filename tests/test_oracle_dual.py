@@ -207,3 +207,25 @@ def test_bf16_rounding_pins():
     z = np.concatenate([x, [1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 2.0 ** -134, 2.0 ** -133, 3 * 2.0 ** -135,
                             (2 - 2 ** -8) * 2.0 ** 127, -0.0, 0.0, np.inf, -np.inf]])
     np.testing.assert_array_equal(P.round_bf16(z), np.array([P.round_bf16_scalar(v) for v in z]))
+
+
+def test_exact_gradient_and_refinement():
+    """The exact-arithmetic gradient agrees with the FP64 closed form where no
+    cancellation occurs (alpha far from the optimum), and after refinement the
+    exact gradient at the dual optimum is at rounding level of its terms."""
+    rng = np.random.default_rng(31)
+    n, d, m, lam = 24, 8, 4, 0.1
+    X = rng.integers(-40, 41, size=(n, d)) / 16.0
+    y = rng.standard_normal(n)
+    a_far = rng.standard_normal(n)
+    g_plain = X @ ((X.T @ a_far) ** (m - 1)) + lam * a_far - y
+    g_exact = D.dual_grad_exact_linear(X, y, lam, m, a_far)
+    np.testing.assert_allclose(g_exact, g_plain, rtol=1e-12, atol=1e-12 * np.abs(g_plain).max())
+    a0, _ = D.solve_linear(X, y, lam, m)
+    a1 = D.refine_linear_exact(X, y, lam, m, a0)
+    u = X.T @ a1
+    terms = np.abs(X) @ (np.abs(u) ** (m - 1)) + lam * np.abs(a1) + np.abs(y)
+    g1 = D.dual_grad_exact_linear(X, y, lam, m, a1)
+    assert np.abs(g1).max() <= 64 * np.finfo(float).eps * terms.max()
+    # the refinement moves the FP64 solution by no more than the FP64 solver's accuracy
+    assert np.linalg.norm(a1 - a0) <= 1e-8 * np.linalg.norm(a0)
