@@ -73,12 +73,61 @@ __device__ __forceinline__ T p_zero() { return T(0); }
 template <>
 __device__ __forceinline__ DD p_zero<DD>() { return DD{0.0, 0.0}; }
 
+// Cross-lane moves within rows of 16 lanes (DPP): xor 1, xor 2, the mirror
+// inside 8 lanes and the mirror inside 16 lanes.  Successive additions with
+// these four patterns sum groups of 2, 4, 8 and 16 lanes.
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+template <int CTRL>
+__device__ __forceinline__ float p_dpp(float a)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(a), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double p_dpp(double a)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(a), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(a), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ DD p_dpp(DD a)
+{
+    return DD{p_dpp<CTRL>(a.hi), p_dpp<CTRL>(a.lo)};
+}
+
 __device__ __forceinline__ DD p_shfl_xor(DD a, int m)
 {
     return DD{__shfl_xor(a.hi, m), __shfl_xor(a.lo, m)};
 }
 __device__ __forceinline__ double p_shfl_xor(double a, int m) { return __shfl_xor(a, m); }
 __device__ __forceinline__ float p_shfl_xor(float a, int m) { return __shfl_xor(a, m); }
+
+// Sum over aligned groups of G lanes (G a power of two <= 64); every lane of a
+// group receives the group's sum (fixed order, so results are reproducible).
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T s)
+{
+    if constexpr (G >= 2) s = p_add(s, p_dpp<kDppXor1>(s));
+    if constexpr (G >= 4) s = p_add(s, p_dpp<kDppXor2>(s));
+    if constexpr (G >= 8) s = p_add(s, p_dpp<kDppHalfMirror>(s));
+    if constexpr (G >= 16) s = p_add(s, p_dpp<kDppMirror>(s));
+    if constexpr (G >= 32) s = p_add(s, p_shfl_xor(s, 16));
+    if constexpr (G >= 64) s = p_add(s, p_shfl_xor(s, 32));
+    return s;
+}
+
+// Pairwise sum of N consecutive values v[0..N).
+template <int N, typename T, typename F>
+__device__ __forceinline__ T tree_sum(F v)
+{
+    if constexpr (N == 1) return v(0);
+    else {
+        constexpr int H = N / 2;
+        const T a = tree_sum<H, T>(v);
+        const T b = tree_sum<N - H, T>([&](int i) { return v(H + i); });
+        return p_add(a, b);
+    }
+}
 
 // Coefficient types: DD carries a low part (exact quotients alpha/r), plain
 // modes use the value type.
@@ -484,7 +533,18 @@ struct Pass {
         }
         // ---- phase 2: in-unit column sums and row partials.  Rows past the
         // batch run with zero row coefficients (their row partials are never
-        // read), so the loads above are not tied to per-row branches.
+        // read), so the loads above are not tied to per-row branches.  Plain
+        // modes accumulate odd rows into a second set of column sums, halving
+        // the dependent chains.
+        constexpr bool SPLIT = MODE != ACC_DD;
+        PT Uo[BT][SPLIT ? SEG : 1], Udo[BT][SPLIT ? SEG : 1];
+#pragma unroll
+        for (int bt = 0; bt < BT; ++bt)
+#pragma unroll
+            for (int j = 0; j < (SPLIT ? SEG : 1); ++j) {
+                Uo[bt][j] = p_zero<PT>();
+                Udo[bt][j] = p_zero<PT>();
+            }
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             const bool live = r < nrows;
@@ -505,15 +565,17 @@ struct Pass {
                     const int b = KB + j;
                     VIn x = val[r][j];
                     if (j == 0) x = tie_scale(d, x);
-                    acc_cv(U[bt][b], ak, x);
+                    PT &u = (SPLIT && (r & 1)) ? Uo[bt][SPLIT ? j : 0] : U[bt][b];
+                    PT &ud = (SPLIT && (r & 1)) ? Udo[bt][SPLIT ? j : 0] : Ud[bt][b];
+                    acc_cv(u, ak, x);
                     acc_cv(part, a_l[bt][b], x);
                     if constexpr (HVP) {
-                        acc_cv(Ud[bt][b], vk, x);
+                        acc_cv(ud, vk, x);
                         acc_cv(partd, v_l[bt][b], x);
                         if constexpr (ATAN) {
                             VIn xd = vald[r][j];
                             if (j == 0) xd = tie_scale(d, xd);
-                            acc_cv(Ud[bt][b], ak, xd);
+                            acc_cv(ud, ak, xd);
                             acc_cv(partd, a_l[bt][b], xd);
                         }
                     }
@@ -522,17 +584,24 @@ struct Pass {
                 if constexpr (HVP) buf[(r * NC + BT + bt) * kWave + lane] = partd;
             }
         }
+        if constexpr (SPLIT) {
+#pragma unroll
+            for (int bt = 0; bt < BT; ++bt)
+#pragma unroll
+                for (int j = 0; j < SEG; ++j) {
+                    U[bt][KB + j] = p_add(U[bt][KB + j], Uo[bt][j]);
+                    if constexpr (HVP) Ud[bt][KB + j] = p_add(Ud[bt][KB + j], Udo[bt][j]);
+                }
+        }
         __builtin_amdgcn_wave_barrier();
         // ---- transposed reduction: lanes [r LPR, (r+1) LPR) sum row r
         {
             const int r = lane / LPR, seg = lane % LPR;
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                PT s = p_zero<PT>();
-#pragma unroll
-                for (int j = 0; j < RB; ++j) s = p_add(s, buf[(r * NC + c) * kWave + seg * RB + j]);
-#pragma unroll
-                for (int m = 1; m < LPR; m <<= 1) s = p_add(s, p_shfl_xor(s, m));
+                const PT *src = buf + (r * NC + c) * kWave + seg * RB;
+                PT s = tree_sum<RB, PT>([&](int j) { return src[j]; });
+                s = group_sum<LPR>(s);
                 if (seg == 0) sbatch[r * NC + c] = s;
             }
         }
@@ -720,11 +789,9 @@ __global__ void __launch_bounds__(256) pair_kernel(PairParams p)
             // S_{P'}: wave reduction, written by lane 0
 #pragma unroll
             for (int bt = 0; bt < BT; ++bt) {
-                PT s = ps.unitS[bt];
-                for (int m = 1; m < kWave; m <<= 1) s = p_add(s, p_shfl_xor(s, m));
+                const PT s = group_sum<kWave>(ps.unitS[bt]);
                 PT sd = ps.unitSd[bt];
-                if constexpr (HVP)
-                    for (int m = 1; m < kWave; m <<= 1) sd = p_add(sd, p_shfl_xor(sd, m));
+                if constexpr (HVP) sd = group_sum<kWave>(sd);
                 if (lane == 0 && b0 + bt < p.B) {
                     store_s(p.S_out, (int64_t)(b0 + bt) * p.units + uidx, s);
                     if constexpr (HVP) store_s(p.Sd_out, (int64_t)(b0 + bt) * p.units + uidx, sd);
