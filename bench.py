@@ -29,6 +29,55 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_hvp_n256_m4_f64.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2003_10482_amd", "csrc", "tk_contract.hip")
+
+
+def source_digest() -> str:
+    import hashlib
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant pass from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs, or None when the kernel source has changed
+    since they were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256_16") != source_digest():
+        return None
+    return float(t["fetch_bytes_per_launch"]) + float(t["write_bytes_per_launch"])
+
+
+def pass_only(count: int) -> int:
+    """The dominant kernel alone, for counter runs: `count` directional-derivative
+    passes over the FP64 tensor of the benchmark workload (same launch shape as
+    in the solve), then one 1 GiB device-to-device copy whose counters give the
+    scale of FETCH_SIZE and WRITE_SIZE."""
+    import torch
+
+    import paper_2003_10482_amd as tk
+    from synth import make_workload
+
+    dev = torch.device("cuda:0")
+    wl = make_workload("c2_n256_m4")
+    X = torch.as_tensor(wl.X, device=dev)
+    K = tk.build_packed_tensor(X, wl.m, dtype="f64")
+    g = torch.Generator(device="cpu").manual_seed(5)
+    a = torch.randn(1, wl.n, generator=g, dtype=torch.float64).to(dev)
+    v = torch.randn(1, wl.n, generator=g, dtype=torch.float64).to(dev)
+    for _ in range(count):
+        tk.hvp(K, a, v)
+    src = torch.ones(2 ** 27, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"pass_only": count, "packed_bytes": K.count * 8, "copy_bytes": 2 ** 30}))
+    return 0
 
 
 def cpu_baseline(passes: int = 2) -> dict:
@@ -57,11 +106,15 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pass-only", type=int, default=0,
+                    help="run only this many passes of the dominant kernel (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path", file=sys.stderr)
         return 2
+
+    if args.pass_only:
+        return pass_only(args.pass_only)
 
     import numpy as np
     import torch
@@ -128,7 +181,8 @@ def main() -> int:
                   "cg_iters": infos[0]["cg_iters"], "grad_norm": infos[0]["grad_norm"],
                   "status": infos[0]["status"], "support_f1": f1, "support_size": len(sel)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic() if kind == "hvp" else None,
                      "kernel": f"packed-tensor pass ({kind})", "avg_launch_ms": avg_ms,
                      "launches": launches},
     }
