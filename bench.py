@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_hvp_n256_m4_f64.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2003_10482_amd", "csrc", "tk_contract.hip")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2003_10482_amd", "csrc", "tk_pass.hpp")
 
 
 def source_digest() -> str:

@@ -47,6 +47,10 @@ int pass_groups(int q, int64_t n, int64_t count, int resident);
 const int64_t *pass_plan(int q, int64_t n, int groups, int *err);
 hipError_t launch_pass(int q, int in_kind, int mode, int hv, int bt, const PairParams &pp,
                        int groups, hipStream_t st);
+// per accumulation mode (separate translation units)
+hipError_t launch_pass_dd(int q, int in_kind, int hv, int bt, const PairParams &pp, int groups, hipStream_t st);
+hipError_t launch_pass_f64(int q, int in_kind, int hv, int bt, const PairParams &pp, int groups, hipStream_t st);
+hipError_t launch_pass_f32(int q, int in_kind, int hv, int bt, const PairParams &pp, int groups, hipStream_t st);
 hipError_t launch_reduce(const ReduceParams &rp, int64_t B, hipStream_t st);
 
 }  // namespace tk
