@@ -134,6 +134,15 @@ typedef struct {
                             compensated gradients until tol is met (may be NULL) */
     int polish_dtype;    /* dtype of polish_K (must be TK_F64 when set) */
     int verbose;         /* print one line per Newton iteration to stderr */
+    int precond;         /* 1 (default): CG preconditioned with (J + lambda I)^{-1}, J the
+                            Hessian of the contraction assembled from n directional
+                            derivatives (FP32 arithmetic) and inverted on the host (n <= 256);
+                            0: plain CG */
+    int precond_refresh; /* re-assemble J after a Newton step that needed more than this
+                            many CG steps (default 8) */
+    int continuation;    /* B > 1: 1 (default) solves the lambdas one after another from the
+                            largest down, each started from the previous solution and keeping
+                            its J; 0: all lambdas in lock step, sharing every pass */
 } tk_solve_opts;
 
 typedef struct {
@@ -144,6 +153,9 @@ typedef struct {
     double objective;    /* final D(alpha) */
     double alpha_norm;
     int status;          /* TK_OK or TK_ENOCONV / TK_ENAN for this lambda */
+    int hess_passes;     /* passes over the packed tensor spent on Hessian assembly (one per
+                            tile of 4 directions) */
+    int precond_updates; /* preconditioner factorisations for this lambda */
 } tk_solve_info;
 
 void tk_solve_opts_default(tk_solve_opts *h_opts);
@@ -152,10 +164,11 @@ int tk_solve_workspace(int64_t n, int m, int64_t B, int dtype, size_t *h_bytes);
 
 /*
  * Minimise the dual D(alpha) of eq. dual_tensor_kernel for B regularisation
- * values at once (a lambda path), by truncated Newton: each Newton step solves
- * (J(alpha) + lambda I) p = -grad D with conjugate gradients whose products are
- * tk_hvp passes, followed by an Armijo backtracking line search on D.  All B
- * problems share every pass over d_K.  d_y is the FP64 response [n]; h_lambdas
+ * values (a lambda path), by truncated Newton: each Newton step solves
+ * (J(alpha) + lambda I) p = -grad D with preconditioned conjugate gradients
+ * whose products are tk_hvp passes, followed by an Armijo backtracking line
+ * search on D.  With opts->continuation the lambdas are solved in decreasing
+ * order from each other's solutions; otherwise all B share every pass.  d_y is the FP64 response [n]; h_lambdas
  * holds B values (host); d_alpha [B*n] receives the solutions (and holds the
  * warm start when opts->warm_start).  h_info receives B records.
  * Synchronises: returns when every lambda has converged or hit its limits.

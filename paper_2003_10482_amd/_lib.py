@@ -33,6 +33,9 @@ class SolveOpts(ctypes.Structure):
         ("polish_K", c_vp),
         ("polish_dtype", c_int),
         ("verbose", c_int),
+        ("precond", c_int),
+        ("precond_refresh", c_int),
+        ("continuation", c_int),
     ]
 
 
@@ -45,6 +48,8 @@ class SolveInfo(ctypes.Structure):
         ("objective", c_dbl),
         ("alpha_norm", c_dbl),
         ("status", c_int),
+        ("hess_passes", c_int),
+        ("precond_updates", c_int),
     ]
 
     def as_dict(self):

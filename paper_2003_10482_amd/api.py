@@ -144,9 +144,11 @@ def solve_workspace(n: int, m: int, B: int, dtype) -> int:
 def solve_dual(K: PackedTensor, y: torch.Tensor, lambdas: Sequence[float], tol: float = 1e-11,
                max_newton: int = 100, max_cg: int = 2000, fixed_iters: int = 0,
                alpha0: Optional[torch.Tensor] = None, polish: Optional[PackedTensor] = None,
-               verbose: bool = False, raise_on_noconv: bool = False):
-    """Dual solve for every lambda (one shared pass over K per step).  Returns
-    (alpha [B, n], list of info dicts)."""
+               verbose: bool = False, raise_on_noconv: bool = False, precond: bool = True,
+               precond_refresh: int = 8, continuation: bool = True):
+    """Dual solve for every lambda.  Returns (alpha [B, n], list of info dicts).
+    precond: Hessian-preconditioned CG; continuation: lambdas solved from the
+    largest down, each from the previous solution (else in lock step)."""
     y = _dev_f64(y, "y")
     lams = [float(x) for x in lambdas]
     B = len(lams)
@@ -157,6 +159,9 @@ def solve_dual(K: PackedTensor, y: torch.Tensor, lambdas: Sequence[float], tol: 
     opts.max_cg = max_cg
     opts.fixed_iters = fixed_iters
     opts.verbose = int(verbose)
+    opts.precond = int(precond)
+    opts.precond_refresh = int(precond_refresh)
+    opts.continuation = int(continuation)
     if polish is not None:
         opts.polish_K = polish.data.data_ptr()
         opts.polish_dtype = polish.dtype

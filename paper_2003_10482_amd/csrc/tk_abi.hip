@@ -1,6 +1,7 @@
 // C ABI of the packed tensor-kernel library: argument checks, workspace
 // planning, the pass sequence of the contraction, and the host-driven loops of
 // the dual solve and of the model-selection derivative.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
@@ -90,10 +91,11 @@ ContractPlan make_plan(int64_t n, int m, int64_t B, int mode, bool hv, int dtype
         p.q = q;
         p.count = packed_count(n, q);
         p.units = q >= 4 ? packed_count(n, q - 2) : 1;
+        const int bt = pass_bt(i, mode, B);
         p.groups = pass_groups(q, n, p.count,
-                               q >= 4 ? pass_resident(q, pass_in_kind(i, dtype, mode), mode, pass_hv(i, hv),
-                                                      pass_bt(i, mode, B), n)
-                                      : 1);
+                               q >= 4 ? pass_resident(q, pass_in_kind(i, dtype, mode), mode, pass_hv(i, hv), bt, n)
+                                      : 1,
+                               (B + bt - 1) / bt);
         p.s_bytes = q >= 4 ? align256((size_t)B * p.units * inter_size(mode)) : 0;
         p.s_off = off;
         off += p.s_bytes * (hv ? 2 : 1);
@@ -112,6 +114,7 @@ int mode_for(int dtype, int acc, bool hv, int *mode)
         if (hv && (acc == TK_ACC_AUTO || acc == TK_ACC_F64)) { *mode = ACC_PLAIN64; return TK_OK; }
         if (acc == TK_ACC_AUTO || acc == TK_ACC_COMPENSATED) { *mode = ACC_DD; return TK_OK; }
         if (acc == TK_ACC_F64) { *mode = ACC_PLAIN64; return TK_OK; }
+        if (acc == TK_ACC_F32) { *mode = ACC_PLAIN32; return TK_OK; }
         return fail(TK_EINVAL, "accumulation %d not available for FP64 storage", acc);
     }
     if (acc == TK_ACC_AUTO || acc == TK_ACC_F32) { *mode = ACC_PLAIN32; return TK_OK; }
@@ -213,7 +216,8 @@ size_t contract_ws(int64_t n, int m, int64_t B, int dtype)
     // every accumulation mode and both the value and the derivative pass can
     // run in one workspace; grids follow each kernel's occupancy
     size_t w = 0;
-    const int modes[2] = {dtype == TK_F64 ? ACC_DD : ACC_PLAIN32, dtype == TK_F64 ? ACC_PLAIN64 : ACC_PLAIN32};
+    const int modes[3] = {dtype == TK_F64 ? ACC_DD : ACC_PLAIN32, dtype == TK_F64 ? ACC_PLAIN64 : ACC_PLAIN32,
+                          ACC_PLAIN32};
     for (int mode : modes)
         for (int hv = 0; hv < 2; ++hv) {
             const size_t b = make_plan(n, m, B, mode, hv != 0, dtype).bytes;
@@ -359,6 +363,9 @@ void tk_solve_opts_default(tk_solve_opts *o)
     o->max_cg = 2000;
     o->tol = 1e-11;
     o->polish_dtype = TK_F64;
+    o->precond = 1;
+    o->precond_refresh = 8;
+    o->continuation = 1;
 }
 
 }  // extern "C"
@@ -368,10 +375,14 @@ namespace tk {
 namespace {
 
 struct SolveBuffers {
-    double *g, *grad, *x, *r, *dv, *hd, *at, *gt, *stats;
+    double *g, *grad, *x, *r, *dv, *hd, *at, *gt, *z, *stats, *stats2;
+    double *P;             // [B][n][n] preconditioners (inverse Hessians)
+    double *hA, *hV, *hM;  // Hessian assembly: direction blocks [kHessChunk][n] and the matrix [n][n]
     unsigned char *cw;
     size_t cw_bytes;
 };
+
+constexpr int64_t kHessChunk = 64;   // Hessian columns per batched directional-derivative launch
 
 size_t solve_ws(int64_t n, int m, int64_t B, int dtype)
 {
@@ -379,7 +390,11 @@ size_t solve_ws(int64_t n, int m, int64_t B, int dtype)
     size_t cw = contract_ws(n, m, B, dtype);
     const size_t cw64 = contract_ws(n, m, B, TK_F64);   // polish passes on an FP64 tensor
     if (cw64 > cw) cw = cw64;
-    return 8 * vec + align256((size_t)B * 8 * sizeof(double)) + cw;
+    const int64_t hc = n < kHessChunk ? n : kHessChunk;
+    const size_t cwh = contract_ws(n, m, hc, dtype);    // Hessian blocks (FP32 arithmetic)
+    if (cwh > cw) cw = cwh;
+    return 9 * vec + 2 * align256((size_t)B * 8 * sizeof(double)) + align256((size_t)B * n * n * sizeof(double)) +
+           2 * align256((size_t)hc * n * sizeof(double)) + align256((size_t)n * n * sizeof(double)) + cw;
 }
 
 SolveBuffers carve(void *work, int64_t n, int64_t B, size_t total)
@@ -387,20 +402,87 @@ SolveBuffers carve(void *work, int64_t n, int64_t B, size_t total)
     SolveBuffers s{};
     const size_t vec = align256((size_t)B * n * sizeof(double));
     unsigned char *w = reinterpret_cast<unsigned char *>(work);
-    double **v[8] = {&s.g, &s.grad, &s.x, &s.r, &s.dv, &s.hd, &s.at, &s.gt};
-    for (int i = 0; i < 8; ++i) *v[i] = reinterpret_cast<double *>(w + i * vec);
-    s.stats = reinterpret_cast<double *>(w + 8 * vec);
-    const size_t used = 8 * vec + align256((size_t)B * 8 * sizeof(double));
+    double **v[9] = {&s.g, &s.grad, &s.x, &s.r, &s.dv, &s.hd, &s.at, &s.gt, &s.z};
+    for (int i = 0; i < 9; ++i) *v[i] = reinterpret_cast<double *>(w + i * vec);
+    size_t used = 9 * vec;
+    s.stats = reinterpret_cast<double *>(w + used);
+    used += align256((size_t)B * 8 * sizeof(double));
+    s.stats2 = reinterpret_cast<double *>(w + used);
+    used += align256((size_t)B * 8 * sizeof(double));
+    s.P = reinterpret_cast<double *>(w + used);
+    used += align256((size_t)B * n * n * sizeof(double));
+    const int64_t hc = n < kHessChunk ? n : kHessChunk;
+    s.hA = reinterpret_cast<double *>(w + used);
+    used += align256((size_t)hc * n * sizeof(double));
+    s.hV = reinterpret_cast<double *>(w + used);
+    used += align256((size_t)hc * n * sizeof(double));
+    s.hM = reinterpret_cast<double *>(w + used);
+    used += align256((size_t)n * n * sizeof(double));
     s.cw = w + used;
     s.cw_bytes = total - used;
     return s;
 }
 
+// Inverse of a symmetric positive definite matrix (row-major, n x n) through
+// its Cholesky factor A = L L^T: W = L^{-1} by forward substitution, then
+// A^{-1} = W^T W.  Returns false when a pivot is not positive.
+bool spd_inverse(std::vector<double> &A, int n)
+{
+    std::vector<double> L((size_t)n * n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        const double *Lj = &L[(size_t)j * n];
+        double d = A[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k) d -= Lj[k] * Lj[k];
+        if (!(d > 0) || !std::isfinite(d)) return false;
+        const double ljj = std::sqrt(d);
+        L[(size_t)j * n + j] = ljj;
+        for (int i = j + 1; i < n; ++i) {
+            const double *Li = &L[(size_t)i * n];
+            double t = A[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) t -= Li[k] * Lj[k];
+            L[(size_t)i * n + j] = t / ljj;
+        }
+    }
+    // column c of W: W[c][c] = 1/L[c][c], W[i][c] = -(sum_{c<=k<i} L[i][k] W[k][c]) / L[i][i];
+    // kept transposed (Wt[c][i] = W[i][c]) so the inner sums run over contiguous memory
+    std::vector<double> Wt((size_t)n * n, 0.0);
+    for (int c = 0; c < n; ++c) {
+        double *wc = &Wt[(size_t)c * n];
+        wc[c] = 1.0 / L[(size_t)c * n + c];
+        for (int i = c + 1; i < n; ++i) {
+            const double *Li = &L[(size_t)i * n];
+            double t = 0.0;
+            for (int k = c; k < i; ++k) t += Li[k] * wc[k];
+            wc[i] = -t / Li[i];
+        }
+    }
+    // (W^T W)[r][c] = sum_{k >= max(r,c)} W[k][r] W[k][c] = Wt[r] . Wt[c] over k >= max(r, c)
+    for (int r = 0; r < n; ++r)
+        for (int c = 0; c <= r; ++c) {
+            const double *wr = &Wt[(size_t)r * n], *wc = &Wt[(size_t)c * n];
+            double t = 0.0;
+            for (int k = r; k < n; ++k) t += wr[k] * wc[k];
+            A[(size_t)r * n + c] = t;
+            A[(size_t)c * n + r] = t;
+        }
+    return true;
+}
+
+// Host copy of the last assembled Hessian J = (m-1) K . alpha^{m-2} of one
+// problem; the preconditioner of a lambda is (J + lambda I)^{-1}.
+struct Precond {
+    bool have = false;      // J holds a matrix
+    bool fresh = false;     // ... assembled at the current problem's iterate history
+    std::vector<double> J;
+};
+
 struct ProblemState {
     double lam;
     double D, gn, an, ag, aa, ya;
     int newton, cg, status;
+    int last_cg;       // CG steps of the last Newton step
     bool done;
+    bool pc_ready;     // the device holds this problem's preconditioner
 };
 
 // One batch (B <= kMaxCoefs) of dual solves.  Newton direction from CG on
@@ -408,7 +490,8 @@ struct ProblemState {
 // Armijo backtracking on D.  Gradients: compensated FP64 on FP64 storage,
 // otherwise FP32 accumulation; the optional polish continues on an FP64 tensor.
 int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, const double *lams, int64_t B,
-                const tk_solve_opts &o, double *alpha, tk_solve_info *info, SolveBuffers &sb, hipStream_t st)
+                const tk_solve_opts &o, double *alpha, tk_solve_info *info, SolveBuffers &sb, hipStream_t st,
+                std::vector<Precond> &pc)
 {
     std::vector<ProblemState> ps(B);
     for (int64_t b = 0; b < B; ++b) {
@@ -421,9 +504,12 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
         one.c[b] = 1.0;
         minus1.c[b] = -1.0;
     }
-    int passes = 0;
-    std::vector<double> hst(B * 4), hd(B), hr(B);
+    int passes = 0, hess_passes = 0;
+    std::vector<int> pc_updates(B, 0);
+    std::vector<double> hst(B * 4), hd(B), hr(B), hz(B);
     const double inv_m = 1.0 / m;
+    const bool use_pc = o.precond != 0 && n <= 256;
+    const int refresh = o.precond_refresh > 0 ? o.precond_refresh : 8;
 
     auto sync_copy = [&](double *dst, const double *src, size_t cnt) -> int {
         TK_HIP_CHECK(hipMemcpyAsync(dst, src, cnt * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -439,6 +525,57 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
         passes++;
         TK_HIP_CHECK(vec_grad(gdst, a, y, lam, graddst, sb.stats, B, n, st));
         return sync_copy(out.data(), sb.stats, B * 4);
+    };
+
+    // Hessian of problem b at its current alpha into pc[b].J (directional
+    // derivatives along e_0..e_{n-1}, FP32 arithmetic on tensor Kp)
+    auto assemble = [&](const void *Kp, int dt, int64_t b) -> int {
+        const int64_t hc = n < kHessChunk ? n : kHessChunk;
+        for (int64_t j0 = 0; j0 < n; j0 += hc) {
+            const int64_t k = (n - j0) < hc ? (n - j0) : hc;
+            TK_HIP_CHECK(vec_rep_eye(alpha + b * n, sb.hA, sb.hV, j0, k, n, st));
+            int rc = run_contract(Kp, dt, n, m, sb.hA, sb.hV, k, nullptr, sb.hM + j0 * n, ACC_PLAIN32, sb.cw,
+                                  sb.cw_bytes, st);
+            if (rc) return rc;
+            hess_passes += (int)((k + 3) / 4);
+        }
+        Precond &P = pc[b];
+        P.J.resize((size_t)n * n);
+        TK_HIP_CHECK(hipMemcpyAsync(P.J.data(), sb.hM, (size_t)n * n * sizeof(double), hipMemcpyDeviceToHost, st));
+        TK_HIP_CHECK(hipStreamSynchronize(st));
+        for (int64_t i = 0; i < n; ++i)   // FP32 sums are not exactly symmetric
+            for (int64_t j = 0; j < i; ++j) {
+                const double v = 0.5 * (P.J[i * n + j] + P.J[j * n + i]);
+                P.J[i * n + j] = P.J[j * n + i] = v;
+            }
+        P.have = true;
+        P.fresh = true;
+        return TK_OK;
+    };
+    // (J + lambda I)^{-1} of problem b to the device; J = 0 when none is held.
+    // A rounded J may miss positive definiteness by its rounding: shift more.
+    auto upload = [&](int64_t b) -> int {
+        const Precond &P = pc[b];
+        std::vector<double> A((size_t)n * n, 0.0);
+        double tr = 0.0;
+        if (P.have) {
+            A = P.J;
+            for (int64_t i = 0; i < n; ++i) tr += std::fabs(A[i * n + i]);
+        }
+        double shift = ps[b].lam;
+        for (int attempt = 0; attempt < 40; ++attempt) {
+            std::vector<double> T = A;
+            for (int64_t i = 0; i < n; ++i) T[i * n + i] += shift;
+            if (spd_inverse(T, (int)n)) {
+                TK_HIP_CHECK(hipMemcpyAsync(sb.P + b * n * n, T.data(), (size_t)n * n * sizeof(double),
+                                            hipMemcpyHostToDevice, st));
+                TK_HIP_CHECK(hipStreamSynchronize(st));
+                pc_updates[b]++;
+                return TK_OK;
+            }
+            shift = ps[b].lam + (attempt == 0 ? 1e-7 : shift * 10.0) * (tr / (double)n + 1e-300);
+        }
+        return fail(TK_EHIP, "could not factor the preconditioner");
     };
 
     const int phases = (dtype != TK_F64 && o.polish_K) ? 2 : 1;
@@ -490,19 +627,46 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                 any |= !s.done;
             }
             if (!any) break;
-            // ---- CG on (J + lam I) x = -grad for the active problems
+            // ---- preconditioners: (re)assemble the Hessian where the last
+            // Newton step needed many CG steps or none is held yet
+            if (use_pc) {
+                for (int64_t b = 0; b < B; ++b) {
+                    if (ps[b].done) continue;
+                    Precond &P = pc[b];
+                    const bool zero_alpha = !(ps[b].an > 0);
+                    // at alpha = 0 the Hessian of an order m >= 4 dual is lambda I
+                    const bool need = zero_alpha ? (m == 2 && !P.have) : (!P.have || !P.fresh || ps[b].last_cg > refresh);
+                    if (need) {
+                        if ((rc = assemble(Kp, dt, b))) return rc;
+                        if ((rc = upload(b))) return rc;
+                        ps[b].pc_ready = true;
+                    } else if (!ps[b].pc_ready) {
+                        if ((rc = upload(b))) return rc;
+                        ps[b].pc_ready = true;
+                    }
+                }
+            }
+            // ---- preconditioned CG on (J + lam I) x = -grad for the active problems
             Coefs zc{}, act{};
             for (int64_t b = 0; b < B; ++b) act.c[b] = ps[b].done ? 0.0 : 1.0;
             TK_HIP_CHECK(vec_lin2(sb.grad, sb.grad, zero, zero, sb.x, B, n, st));         // x = 0
             TK_HIP_CHECK(vec_lin2(sb.grad, sb.grad, minus1, zero, sb.r, B, n, st));       // r = -grad
-            TK_HIP_CHECK(vec_lin2(sb.r, sb.r, one, zero, sb.dv, B, n, st));               // d = r
-            std::vector<double> rr(B), eta(B);
+            std::vector<double> rz(B), eta(B);
             std::vector<bool> cg_on(B);
+            std::vector<int> cg_steps(B, 0);
+            if (use_pc) {
+                TK_HIP_CHECK(vec_precond(sb.P, sb.r, sb.z, sb.stats2, B, n, st));        // z = P r
+                if ((rc = sync_copy(hz.data(), sb.stats2, B))) return rc;
+            } else {
+                TK_HIP_CHECK(vec_lin2(sb.r, sb.r, one, zero, sb.z, B, n, st));            // z = r
+                for (int64_t b = 0; b < B; ++b) hz[b] = ps[b].gn * ps[b].gn;
+            }
+            TK_HIP_CHECK(vec_lin2(sb.z, sb.z, one, zero, sb.dv, B, n, st));               // d = z
             for (int64_t b = 0; b < B; ++b) {
-                rr[b] = ps[b].gn * ps[b].gn;
+                rz[b] = hz[b];
                 const double f = std::sqrt(ps[b].gn / gn0[b]);
                 eta[b] = std::min(0.5, std::max(f, 1e-12));
-                cg_on[b] = !ps[b].done && rr[b] > 0;
+                cg_on[b] = !ps[b].done && ps[b].gn > 0 && rz[b] > 0;
             }
             const int max_cg = o.max_cg > 0 ? o.max_cg : 2000;
             for (int j = 0; j < max_cg; ++j) {
@@ -521,11 +685,18 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                         cg_on[b] = false;
                         continue;
                     }
-                    a.c[b] = rr[b] / hd[b];
+                    a.c[b] = rz[b] / hd[b];
                     ps[b].cg++;
+                    cg_steps[b]++;
                 }
-                TK_HIP_CHECK(vec_cg_update(sb.x, sb.r, sb.dv, sb.hd, a, sb.stats, B, n, st));
+                TK_HIP_CHECK(vec_cg_update(sb.x, sb.r, sb.dv, sb.hd, a, sb.stats, B, n, st));   // stats = r.r
+                if (use_pc) {
+                    TK_HIP_CHECK(vec_precond(sb.P, sb.r, sb.z, sb.stats2, B, n, st));          // z = P r, r.z
+                } else {
+                    TK_HIP_CHECK(vec_lin2(sb.r, sb.r, one, zero, sb.z, B, n, st));
+                }
                 if ((rc = sync_copy(hr.data(), sb.stats, B))) return rc;
+                if (use_pc && (rc = sync_copy(hz.data(), sb.stats2, B))) return rc;
                 Coefs beta{}, keep{};
                 for (int64_t b = 0; b < B; ++b) {
                     keep.c[b] = 1.0;
@@ -534,12 +705,18 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                         cg_on[b] = false;
                         continue;
                     }
-                    beta.c[b] = hr[b] / rr[b];
-                    rr[b] = hr[b];
+                    const double rzn = use_pc ? hz[b] : hr[b];
+                    beta.c[b] = rzn / rz[b];
+                    rz[b] = rzn;
                 }
-                // d = r + beta d for the problems still iterating (others unchanged: r + 0 d is not used)
-                TK_HIP_CHECK(vec_lin2(sb.r, sb.dv, keep, beta, sb.dv, B, n, st));
+                // d = z + beta d for the problems still iterating
+                TK_HIP_CHECK(vec_lin2(sb.z, sb.dv, keep, beta, sb.dv, B, n, st));
             }
+            for (int64_t b = 0; b < B; ++b)
+                if (!ps[b].done) {
+                    ps[b].last_cg = cg_steps[b];
+                    if (cg_steps[b] > refresh) pc[b].fresh = false;
+                }
             // if CG produced nothing (zero curvature at the first step), fall back to steepest descent
             TK_HIP_CHECK(vec_dot(sb.x, sb.x, n, sb.stats, B, n, st));
             if ((rc = sync_copy(hr.data(), sb.stats, B))) return rc;
@@ -637,6 +814,8 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
         inf.objective = ps[b].D;
         inf.alpha_norm = ps[b].an;
         inf.status = ps[b].status;
+        inf.hess_passes = hess_passes;
+        inf.precond_updates = pc_updates[b];
         if (ps[b].status != TK_OK) overall = ps[b].status;
     }
     return overall;
@@ -680,14 +859,39 @@ int tk_solve_dual(const void *d_K, int dtype, int64_t n, int m, const double *d_
     if (work_bytes < need || !d_work) return fail(TK_ENOMEM, "solve workspace of %zu bytes < %zu", work_bytes, need);
     hipStream_t st = as_stream(stream);
     int overall = TK_OK;
-    for (int64_t b0 = 0; b0 < B; b0 += kMaxCoefs) {
-        const int64_t nb = (B - b0) < kMaxCoefs ? (B - b0) : kMaxCoefs;
-        double *a = d_alpha + b0 * n;
-        if (!o.warm_start) TK_HIP_CHECK(hipMemsetAsync(a, 0, (size_t)nb * n * sizeof(double), st));
-        SolveBuffers sb = carve(d_work, n, nb, work_bytes);
-        rc = solve_batch(d_K, dtype, n, m, d_y, h_lambdas + b0, nb, o, a, h_info + b0, sb, st);
-        if (rc != TK_OK && rc != TK_ENOCONV && rc != TK_ENAN) return rc;
-        if (rc != TK_OK) overall = rc;
+    if (B > 1 && o.continuation) {
+        // lambda path: from the largest lambda down, each solve starts from the
+        // previous solution and keeps its Hessian for the preconditioner
+        std::vector<int64_t> order(B);
+        for (int64_t b = 0; b < B; ++b) order[b] = b;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int64_t u, int64_t v) { return h_lambdas[u] > h_lambdas[v]; });
+        std::vector<Precond> pc(1);
+        SolveBuffers sb = carve(d_work, n, 1, work_bytes);
+        int64_t prev = -1;
+        for (int64_t idx = 0; idx < B; ++idx) {
+            const int64_t b = order[idx];
+            double *a = d_alpha + b * n;
+            if (prev >= 0 && !o.warm_start)
+                TK_HIP_CHECK(hipMemcpyAsync(a, d_alpha + prev * n, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+            else if (prev < 0 && !o.warm_start)
+                TK_HIP_CHECK(hipMemsetAsync(a, 0, n * sizeof(double), st));
+            rc = solve_batch(d_K, dtype, n, m, d_y, h_lambdas + b, 1, o, a, h_info + b, sb, st, pc);
+            if (rc != TK_OK && rc != TK_ENOCONV && rc != TK_ENAN) return rc;
+            if (rc != TK_OK) overall = rc;
+            prev = b;
+        }
+    } else {
+        for (int64_t b0 = 0; b0 < B; b0 += kMaxCoefs) {
+            const int64_t nb = (B - b0) < kMaxCoefs ? (B - b0) : kMaxCoefs;
+            double *a = d_alpha + b0 * n;
+            if (!o.warm_start) TK_HIP_CHECK(hipMemsetAsync(a, 0, (size_t)nb * n * sizeof(double), st));
+            SolveBuffers sb = carve(d_work, n, nb, work_bytes);
+            std::vector<Precond> pc(nb);
+            rc = solve_batch(d_K, dtype, n, m, d_y, h_lambdas + b0, nb, o, a, h_info + b0, sb, st, pc);
+            if (rc != TK_OK && rc != TK_ENOCONV && rc != TK_ENAN) return rc;
+            if (rc != TK_OK) overall = rc;
+        }
     }
     if (overall == TK_ENOCONV) fail(TK_ENOCONV, "at least one lambda did not reach the tolerance");
     if (overall == TK_ENAN) fail(TK_ENAN, "non-finite values met during the solve");

@@ -144,16 +144,19 @@ const int64_t *pass_plan(int q, int64_t n, int groups, int *err)
 }
 
 // Number of workgroups of one pass over an order-q array of `count` entries.
-int pass_groups(int q, int64_t n, int64_t count, int resident)
+int pass_groups(int q, int64_t n, int64_t count, int resident, int64_t tiles)
 {
     if (q == 2) {   // waves split the rows of the single unit: a few rows per wave
         int64_t g = (n + 15) / 16;
         return (int)(g < 1 ? 1 : g);
     }
-    // at least about 4K entries per wave; at most one resident wave slot each
+    // at least about 4K entries per wave; the tiles of vectors (grid rows)
+    // together fill the resident slots once
     int64_t g = (count + 4 * 4096 - 1) / (4 * 4096);
+    int64_t cap = resident / (tiles < 1 ? 1 : tiles);
+    if (cap < 64) cap = 64;
+    if (g > cap) g = cap;
     if (g < 1) g = 1;
-    if (g > resident) g = resident;
     return (int)g;
 }
 

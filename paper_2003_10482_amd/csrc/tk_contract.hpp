@@ -40,9 +40,9 @@ struct ReduceParams {
 
 // Resident workgroups per CU of the kernel that launch_pass selects (cached).
 int pass_resident(int q, int in_kind, int mode, int hv, int bt, int64_t n);
-// Workgroups of one pass: enough to fill every CU to the kernel's occupancy
-// (one wave of persistent work each), fewer for small arrays.
-int pass_groups(int q, int64_t n, int64_t count, int resident);
+// Workgroups of one pass per tile of vectors: together the tiles fill every
+// CU to the kernel's occupancy once, fewer for small arrays.
+int pass_groups(int q, int64_t n, int64_t count, int resident, int64_t tiles);
 // Device copy of the balanced work plan of one pass (cached per (n, q, groups)).
 const int64_t *pass_plan(int q, int64_t n, int groups, int *err);
 hipError_t launch_pass(int q, int in_kind, int mode, int hv, int bt, const PairParams &pp,

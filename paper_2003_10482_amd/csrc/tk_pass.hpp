@@ -308,20 +308,25 @@ struct Pass {
     PT *sbatch;   // [RBMAX][NC] row sums
     int n, lane;
 
-    // Descriptors for the wave's entries from e0 on (16-byte aligned base, so
-    // BF16 dword loads stay aligned); count entries per input array.
+    // Descriptors for the wave's entries, based 64 entries before its first
+    // entry e0 (clamped to the array start, 16-byte aligned so BF16 dword
+    // loads stay aligned); count entries per input array.  An out-of-range
+    // lane of a buffer load zeroes the other lanes of its quad as well, so no
+    // live row may reach below the base: the lanes left of the first row's
+    // diagonal (at most 63 entries back) must stay in range.
     int32_t dshift;   // byte shift of the tangent array's descriptor
     __device__ __forceinline__ void set_base(int64_t e0, int64_t count)
     {
         constexpr int64_t ES = InL::kSize;
         const int64_t end_bytes = (count * ES + 3) & ~(int64_t)3;
-        const uintptr_t a0 = reinterpret_cast<uintptr_t>(A + e0) & ~(uintptr_t)15;
-        e_base = e0 - (int64_t)(reinterpret_cast<uintptr_t>(A + e0) - a0) / ES;
+        const int64_t e1 = e0 >= kWave ? e0 - kWave : 0;
+        const uintptr_t a0 = reinterpret_cast<uintptr_t>(A + e1) & ~(uintptr_t)15;
+        e_base = e1 - (int64_t)(reinterpret_cast<uintptr_t>(A + e1) - a0) / ES;
         rs = make_rsrc(reinterpret_cast<const void *>(a0), end_bytes - e_base * ES);
         dshift = 0;
         if constexpr (ATAN) {
-            const uintptr_t d0 = reinterpret_cast<uintptr_t>(Ad + e0) & ~(uintptr_t)15;
-            const int64_t eb_d = e0 - (int64_t)(reinterpret_cast<uintptr_t>(Ad + e0) - d0) / ES;
+            const uintptr_t d0 = reinterpret_cast<uintptr_t>(Ad + e1) & ~(uintptr_t)15;
+            const int64_t eb_d = e1 - (int64_t)(reinterpret_cast<uintptr_t>(Ad + e1) - d0) / ES;
             rsd = make_rsrc(reinterpret_cast<const void *>(d0), end_bytes - eb_d * ES);
             dshift = (int32_t)((e_base - eb_d) * ES);
         }
@@ -515,16 +520,21 @@ struct Pass {
         constexpr uint32_t ES = (uint32_t)InL::kSize;
         // byte offset (from the descriptor base) of entry (row, column KB*64) of
         // row r; rows past the batch follow the same recurrence and read either
-        // real entries or zeros (their row coefficients are zero below)
+        // real entries or zeros (their row coefficients are zero below).  In
+        // the last block, columns past n re-read column n-1 of the same row, so
+        // the last rows of the array stay inside it.
         uint32_t so = (uint32_t)((off - k - e_base + KB * kWave) * (int64_t)ES);
         const uint32_t vlane = (uint32_t)lane * ES;
+        const int last_col = (NB - 1) * kWave + lane < n ? lane : n - 1 - (NB - 1) * kWave;
+        const uint32_t vtail = (uint32_t)(last_col - lane) * ES;   // 0 but for tail lanes
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             const uint32_t vo = so + vlane;
 #pragma unroll
             for (int j = 0; j < SEG; ++j) {
-                val[r][j] = InL::load_buf(rs, vo + (uint32_t)(j * kWave) * ES);
-                if constexpr (ATAN) vald[r][j] = InL::load_buf(rsd, vo + (uint32_t)dshift + (uint32_t)(j * kWave) * ES);
+                const uint32_t o = vo + (uint32_t)(j * kWave) * ES + (KB + j == NB - 1 ? vtail : 0u);
+                val[r][j] = InL::load_buf(rs, o);
+                if constexpr (ATAN) vald[r][j] = InL::load_buf(rsd, o + (uint32_t)dshift);
             }
             so += (uint32_t)(n - k - 1 - r) * ES;
         }

@@ -148,6 +148,42 @@ inline unsigned grid_for(int64_t n)
     return (unsigned)(g < 1 ? 1 : g > 1024 ? 1024 : g);
 }
 
+// z_b = P_b r_b with P_b a symmetric n x n matrix ([B][n][n]; thread i reads
+// column i, so the loads are coalesced); out_b = r_b . z_b (compensated).
+// One workgroup per vector, n <= 256.
+__global__ void __launch_bounds__(256) precond_kernel(const double *__restrict__ P, const double *__restrict__ r,
+                                                      double *__restrict__ z, double *__restrict__ out, int n)
+{
+    __shared__ DD sh[256];
+    __shared__ double rs[256];
+    const int b = blockIdx.x;
+    const int i = threadIdx.x;
+    if (i < n) rs[i] = r[(int64_t)b * n + i];
+    __syncthreads();
+    DD acc{0, 0};
+    if (i < n) {
+        const double *Pb = P + (int64_t)b * n * n;
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) s = __builtin_fma(Pb[(int64_t)j * n + i], rs[j], s);
+        z[(int64_t)b * n + i] = s;
+        dd_fma(acc, s, rs[i]);
+    }
+    const DD t = block_sum_dd(acc, sh);
+    if (threadIdx.x == 0) out[b] = t.hi + t.lo;
+}
+
+// Directions of a Hessian block: A[i] = alpha (k copies), V[i] = e_{j0+i}.
+__global__ void __launch_bounds__(256) rep_eye_kernel(const double *__restrict__ alpha, double *__restrict__ A,
+                                                      double *__restrict__ V, int j0, int k, int n)
+{
+    const int64_t total = (int64_t)k * n;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(t / n), j = (int)(t % n);
+        A[t] = alpha[j];
+        V[t] = (j == j0 + i) ? 1.0 : 0.0;
+    }
+}
+
 }  // namespace
 
 hipError_t vec_grad(const double *g, const double *alpha, const double *y, const Coefs &lam,
@@ -194,6 +230,23 @@ hipError_t vec_sub(const double *a, const double *b, double *out, int64_t len, h
 hipError_t vec_nonfinite(const double *x, int64_t len, int *flag, hipStream_t st)
 {
     hipLaunchKernelGGL(nonfinite_kernel, dim3(grid_for(len)), dim3(256), 0, st, x, len, flag);
+    return hipGetLastError();
+}
+
+hipError_t vec_precond(const double *P, const double *r, double *z, double *out, int64_t B, int64_t n,
+                       hipStream_t st)
+{
+    if (n > 256) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(precond_kernel, dim3((unsigned)B), dim3(256), 0, st, P, r, z, out, (int)n);
+    return hipGetLastError();
+}
+
+hipError_t vec_rep_eye(const double *alpha, double *A, double *V, int64_t j0, int64_t k, int64_t n, hipStream_t st)
+{
+    const int64_t total = k * n;
+    const int blocks = (int)((total + 255) / 256 < 1024 ? (total + 255) / 256 : 1024);
+    hipLaunchKernelGGL(rep_eye_kernel, dim3(blocks < 1 ? 1 : blocks), dim3(256), 0, st, alpha, A, V, (int)j0, (int)k,
+                       (int)n);
     return hipGetLastError();
 }
 

@@ -116,6 +116,35 @@ def test_contract_reduced_precision(n, m, storage):
         assert np.max(np.abs(g[b] - ref_r) / E) <= 64 * U32 * np.sqrt(depth)
 
 
+@pytest.mark.parametrize("n,m", [(129, 4), (200, 4), (256, 2), (150, 2)])
+@pytest.mark.parametrize("storage", ["f32", "bf16", "f64-f32"])
+def test_reduced_precision_relative(n, m, storage):
+    """FP32 accumulation against the FP64 contraction of the same stored values,
+    relative to max |g| (the absolute-term bound of the test above is loose
+    enough to hide lost entries).  Sizes cover 3 and 4 column blocks, tails and
+    the first rows of many waves; one-hot directions probe single entries."""
+    K = random_symmetric_packed_values(L.packed_count(n, m), seed=11 * n + m)
+    kind = "f64" if storage == "f64-f32" else storage
+    Kd, Kr = _packed_dev(K, n, m, kind)
+    acc = tk.ACC_F32 if storage == "f64-f32" else tk.ACC_AUTO
+    nb = 5 if m == 2 else 2
+    A = random_alpha(n, seed=5 * n + m, batch=nb)
+    g = to_np(tk.contract(Kd, to_dev(A), acc=acc))
+    for b in range(nb):
+        ref = T.contract_packed(Kr, n, m, A[b])
+        assert np.max(np.abs(g[b] - ref)) <= 1e-4 * np.max(np.abs(ref)), (n, m, storage, b)
+    # one-hot directions: h = J e_c, column c of the Jacobian
+    cols = [0, 3, 64, 67, 70, 127, n // 2 + 1, n - 2, n - 1] if m == 2 else [67, n - 1]
+    V = np.zeros((len(cols), n))
+    for i, c in enumerate(cols):
+        V[i, c] = 1.0
+    Ab = np.repeat(A[:1], len(cols), axis=0)
+    h = to_np(tk.hvp(Kd, to_dev(Ab), to_dev(V), acc=acc))
+    for i in range(len(cols)):
+        ref = T.hvp_packed(Kr, n, m, Ab[i], V[i])
+        assert np.max(np.abs(h[i] - ref)) <= 1e-4 * np.max(np.abs(ref)), (n, m, storage, cols[i])
+
+
 @pytest.mark.parametrize("n,m", [(7, 4), (70, 4), (130, 4), (5, 6), (40, 6), (9, 2)])
 def test_hvp_f64_random_tensor(n, m):
     K = random_symmetric_packed_values(L.packed_count(n, m), seed=n * m + 1)
