@@ -136,10 +136,10 @@ typedef struct {
     int verbose;         /* print one line per Newton iteration to stderr */
     int precond;         /* 1 (default): CG preconditioned with (J + lambda I)^{-1}, J the
                             Hessian of the contraction assembled from n directional
-                            derivatives (FP32 arithmetic) and inverted on the host (n <= 256);
-                            0: plain CG */
+                            derivatives (FP64 on the FP64 tensor or polish tensor) and
+                            inverted on the host (n <= 256); 0: plain CG */
     int precond_refresh; /* re-assemble J after a Newton step that needed more than this
-                            many CG steps (default 8) */
+                            many CG steps (default 12) */
     int continuation;    /* B > 1: 1 (default) solves the lambdas one after another from the
                             largest down, each started from the previous solution and keeping
                             its J; 0: all lambdas in lock step, sharing every pass */

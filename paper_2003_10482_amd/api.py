@@ -145,7 +145,7 @@ def solve_dual(K: PackedTensor, y: torch.Tensor, lambdas: Sequence[float], tol: 
                max_newton: int = 100, max_cg: int = 2000, fixed_iters: int = 0,
                alpha0: Optional[torch.Tensor] = None, polish: Optional[PackedTensor] = None,
                verbose: bool = False, raise_on_noconv: bool = False, precond: bool = True,
-               precond_refresh: int = 8, continuation: bool = True):
+               precond_refresh: int = 12, continuation: bool = True):
     """Dual solve for every lambda.  Returns (alpha [B, n], list of info dicts).
     precond: Hessian-preconditioned CG; continuation: lambdas solved from the
     largest down, each from the previous solution (else in lock step)."""

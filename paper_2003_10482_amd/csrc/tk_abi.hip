@@ -175,7 +175,8 @@ int run_contract(const void *K, int dtype, int64_t n, int m, const double *alpha
             if (g_timing_on && hipEventCreate(&tl.a) == hipSuccess && hipEventCreate(&tl.b) == hipSuccess) {
                 timed = true;
                 tl.kind = hv ? 1 : 0;
-                tl.bytes = (double)pp.count * (double)dtype_size(dtype);
+                // one read of the stored tensor per tile of bt vectors
+                tl.bytes = (double)pp.count * (double)dtype_size(dtype) * (double)((B + bt - 1) / bt);
                 hipEventRecord(tl.a, st);
             }
         }
@@ -364,7 +365,7 @@ void tk_solve_opts_default(tk_solve_opts *o)
     o->tol = 1e-11;
     o->polish_dtype = TK_F64;
     o->precond = 1;
-    o->precond_refresh = 8;
+    o->precond_refresh = 12;
     o->continuation = 1;
 }
 
@@ -391,7 +392,9 @@ size_t solve_ws(int64_t n, int m, int64_t B, int dtype)
     const size_t cw64 = contract_ws(n, m, B, TK_F64);   // polish passes on an FP64 tensor
     if (cw64 > cw) cw = cw64;
     const int64_t hc = n < kHessChunk ? n : kHessChunk;
-    const size_t cwh = contract_ws(n, m, hc, dtype);    // Hessian blocks (FP32 arithmetic)
+    size_t cwh = contract_ws(n, m, hc, dtype);          // Hessian blocks
+    const size_t cwh64 = contract_ws(n, m, hc, TK_F64);  // ... on the FP64 polish tensor
+    if (cwh64 > cwh) cwh = cwh64;
     if (cwh > cw) cw = cwh;
     return 9 * vec + 2 * align256((size_t)B * 8 * sizeof(double)) + align256((size_t)B * n * n * sizeof(double)) +
            2 * align256((size_t)hc * n * sizeof(double)) + align256((size_t)n * n * sizeof(double)) + cw;
@@ -527,17 +530,23 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
         return sync_copy(out.data(), sb.stats, B * 4);
     };
 
-    // Hessian of problem b at its current alpha into pc[b].J (directional
-    // derivatives along e_0..e_{n-1}, FP32 arithmetic on tensor Kp)
+    // Hessian of problem b at its current alpha into pc[b].J: directional
+    // derivatives along e_0..e_{n-1}.  At the dual optimum the products behind
+    // J cancel by orders of magnitude (alpha is large where X^T alpha is not),
+    // so they run in FP64 on an FP64 tensor (the polish tensor when the solve
+    // runs on reduced storage); FP32 only when no FP64 tensor exists.
     auto assemble = [&](const void *Kp, int dt, int64_t b) -> int {
+        const void *Kh = (dt != TK_F64 && o.polish_K) ? o.polish_K : Kp;
+        const int dth = (dt != TK_F64 && o.polish_K) ? TK_F64 : dt;
+        const int hmode = dth == TK_F64 ? ACC_PLAIN64 : ACC_PLAIN32;
         const int64_t hc = n < kHessChunk ? n : kHessChunk;
         for (int64_t j0 = 0; j0 < n; j0 += hc) {
             const int64_t k = (n - j0) < hc ? (n - j0) : hc;
             TK_HIP_CHECK(vec_rep_eye(alpha + b * n, sb.hA, sb.hV, j0, k, n, st));
-            int rc = run_contract(Kp, dt, n, m, sb.hA, sb.hV, k, nullptr, sb.hM + j0 * n, ACC_PLAIN32, sb.cw,
+            int rc = run_contract(Kh, dth, n, m, sb.hA, sb.hV, k, nullptr, sb.hM + j0 * n, hmode, sb.cw,
                                   sb.cw_bytes, st);
             if (rc) return rc;
-            hess_passes += (int)((k + 3) / 4);
+            hess_passes += (int)(hmode == ACC_PLAIN32 ? (k + 3) / 4 : k);
         }
         Precond &P = pc[b];
         P.J.resize((size_t)n * n);

@@ -89,26 +89,59 @@ def test_nystrom_fp32_with_fp64_polish():
     _same_support(w, w_ref)
 
 
-@pytest.mark.parametrize("storage", ["f64", "bf16"])
-def test_lambda_path(storage):
-    """λ path of the n=256 workload solved in lock step (every pass shared by
-    all λ); reduced precision is followed by an FP64 polish."""
+def test_lambda_path_fp64_all_64():
+    """The 64-value lambda path of the n=256 workload (1e-4 .. 1), FP64 tensor,
+    solved from the largest lambda down with Hessian-preconditioned Newton:
+    every lambda converges, w matches the oracle's path and the 2-std supports
+    (and F1 against the planted support) are identical."""
     wl = make_workload("c4_lampath")
-    # the upper part of the path: below 1e-2 the truncated-Newton solver needs
-    # tens of thousands of passes (kappa(H) ~ 1e6..1e7), see DESIGN.md
-    lams = wl.lambdas[[42, 52, 63]]
     X, y = to_dev(wl.X), to_dev(wl.y)
-    K64 = tk.build_packed_tensor(X, 4)
-    K = K64 if storage == "f64" else tk.build_packed_tensor(X, 4, dtype=storage)
-    alpha, infos = tk.solve_dual(K, y, lams, tol=1e-10, polish=None if storage == "f64" else K64)
+    K = tk.build_packed_tensor(X, 4)
+    alpha, infos = tk.solve_dual(K, y, wl.lambdas, tol=1e-10)
     W = to_np(tk.primal_weights(X, alpha, 4))
-    for b, lam in enumerate(lams):
+    A_ref, _ = D.solve_path(wl.X, wl.y, wl.lambdas, 4)
+    for b, lam in enumerate(wl.lambdas):
         assert infos[b]["status"] == 0, (lam, infos[b])
-        ref, _ = D.solve_linear(wl.X, wl.y, lam, 4)
-        w_ref = D.primal_from_dual(wl.X, ref, 4)
-        assert _rel(W[b], w_ref) <= 1e-7, lam
+        w_ref = D.primal_from_dual(wl.X, A_ref[b], 4)
+        assert _rel(W[b], w_ref) <= 1e-6, lam
         m1, m2 = _same_support(W[b], w_ref)
         assert D.f1_score(m1, wl.support) == D.f1_score(m2, wl.support)
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_lambda_path_reduced_with_polish(storage):
+    """Reduced-precision storage along the path (every 9th lambda), each
+    lambda finished on the FP64 tensor."""
+    wl = make_workload("c4_lampath")
+    lams = wl.lambdas[::9]
+    X, y = to_dev(wl.X), to_dev(wl.y)
+    K64 = tk.build_packed_tensor(X, 4)
+    K = tk.build_packed_tensor(X, 4, dtype=storage)
+    alpha, infos = tk.solve_dual(K, y, lams, tol=1e-10, polish=K64)
+    W = to_np(tk.primal_weights(X, alpha, 4))
+    A_ref, _ = D.solve_path(wl.X, wl.y, lams, 4)
+    for b, lam in enumerate(lams):
+        assert infos[b]["status"] == 0, (lam, infos[b])
+        w_ref = D.primal_from_dual(wl.X, A_ref[b], 4)
+        assert _rel(W[b], w_ref) <= 1e-6, lam
+        m1, m2 = _same_support(W[b], w_ref)
+        assert D.f1_score(m1, wl.support) == D.f1_score(m2, wl.support)
+
+
+def test_lambda_path_lock_step_matches_continuation():
+    """The lock-step mode (all lambdas share every pass) reaches the same
+    solutions as the continuation mode on the upper part of the path."""
+    wl = make_workload("c4_lampath")
+    lams = wl.lambdas[[40, 48, 56, 63]]
+    X, y = to_dev(wl.X), to_dev(wl.y)
+    K = tk.build_packed_tensor(X, 4)
+    a1, i1 = tk.solve_dual(K, y, lams, tol=1e-11, continuation=True)
+    a2, i2 = tk.solve_dual(K, y, lams, tol=1e-11, continuation=False)
+    for b in range(len(lams)):
+        assert i1[b]["status"] == 0 and i2[b]["status"] == 0
+        w1 = to_np(tk.primal_weights(X, a1[b], 4))
+        w2 = to_np(tk.primal_weights(X, a2[b], 4))
+        assert _rel(w1, w2) <= 1e-9
 
 
 def test_order6_derivatives_full_size():
