@@ -3,9 +3,12 @@
 One step = one pass of the whole hot path on the workload n=256, d=200, m=4,
 lambda=1e-2 (synthetic, Section 5.4 data model, seed 1002), inputs resident in
 HBM: build the packed FP64 tensor (C(259,4) = 183,181,376 entries, 1.47 GB),
-solve the dual to ||grad D|| <= 1e-11 lambda ||alpha|| with the truncated-Newton
-solver (every Newton / CG / line-search step streams the packed tensor once),
-recover w = (X^T alpha)^3, take the 2-std support and predict on X.
+solve the dual to ||grad D|| <= 1e-11 lambda ||alpha|| with the
+Hessian-preconditioned truncated-Newton solver (every gradient, CG,
+line-search and Hessian-column step streams the packed tensor), recover
+w = (X^T alpha)^3, take the 2-std support and predict on X.  After the timed
+steps, the 64-value lambda path of the same data is solved and timed
+separately ("lambda_path").
 
 value = passes over the packed tensor per second across the timed steps
         (K . alpha^{m-1} contractions and their directional derivatives).
@@ -100,12 +103,50 @@ def cpu_baseline(passes: int = 2) -> dict:
                       f"single-threaded C oracle, {dt:.1f} s"}
 
 
+def lambda_path(tk, torch, dev) -> dict:
+    """Solve time of the 64-value lambda path of the same data (1e-4 .. 1), FP64
+    tensor, from the largest lambda down; support recovery per lambda against
+    the planted support.  Runs after the timed steps."""
+    import numpy as np
+
+    from synth import make_workload
+
+    wl = make_workload("c4_lampath")
+    X = torch.as_tensor(wl.X, device=dev)
+    y = torch.as_tensor(wl.y, device=dev)
+    K = tk.build_packed_tensor(X, wl.m, dtype="f64")
+    out = {"lambdas": len(wl.lambdas), "range": [float(wl.lambdas.min()), float(wl.lambdas.max())]}
+    true = set(wl.support.tolist())
+    for tol in (1e-10, 1e-4):
+        tk.solve_dual(K, y, wl.lambdas[-2:], tol=tol)   # warm the plan caches
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        alpha, infos = tk.solve_dual(K, y, wl.lambdas, tol=tol)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        W = tk.primal_weights(X, alpha, wl.m)
+        mask, _ = tk.support(W)
+        m = mask.cpu().numpy().astype(bool)
+        f1 = []
+        for b in range(len(wl.lambdas)):
+            sel = set(np.flatnonzero(m[b]).tolist())
+            tp = len(sel & true)
+            f1.append(0.0 if tp == 0 else 2 * tp / (len(sel) + len(true)))
+        out[f"tol_{tol:g}"] = {"seconds": dt, "passes": sum(i["passes"] + i["hess_passes"] for i in infos),
+                               "newton_iters": sum(i["newton_iters"] for i in infos),
+                               "all_converged": all(i["status"] == 0 for i in infos),
+                               "support_f1_min": min(f1), "support_f1_mean": float(np.mean(f1))}
+    del K
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-path", action="store_true", help="skip the 64-lambda path (outside the timed steps)")
     ap.add_argument("--pass-only", type=int, default=0,
                     help="run only this many passes of the dominant kernel (for counter runs)")
     args = ap.parse_args()
@@ -145,7 +186,7 @@ def main() -> int:
     t0 = time.perf_counter()
     for _ in range(args.steps):
         alpha, infos, W, mask, f = step()
-        passes += infos[0]["passes"]
+        passes += infos[0]["passes"] + infos[0]["hess_passes"]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     timing = tk.timing_stop()
@@ -178,11 +219,15 @@ def main() -> int:
                    "n": wl.n, "d": wl.d, "m": wl.m, "lambda": wl.lam, "packed_entries": count,
                    "packed_bytes": count * 8},
         "solve": {"passes_per_step": passes / args.steps, "newton_iters": infos[0]["newton_iters"],
-                  "cg_iters": infos[0]["cg_iters"], "grad_norm": infos[0]["grad_norm"],
+                  "cg_iters": infos[0]["cg_iters"], "hessian_passes": infos[0]["hess_passes"],
+                  "grad_norm": infos[0]["grad_norm"],
                   "status": infos[0]["status"], "support_f1": f1, "support_size": len(sel)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic() if kind == "hvp" else None,
+                     # counters are per read of the tensor; launches here average
+                     # kbytes / launches / (C * 8) reads
+                     "traffic": (measured_traffic() * (kbytes / max(launches, 1)) / (count * 8.0)
+                                 if kind == "hvp" and measured_traffic() is not None else None),
                      "kernel": f"packed-tensor pass ({kind})", "avg_launch_ms": avg_ms,
                      "launches": launches},
     }
@@ -191,6 +236,8 @@ def main() -> int:
         l2, ms2, b2 = timing[other]
         out["roofline"]["other_pass"] = {"kind": other, "avg_launch_ms": ms2 / l2,
                                          "achieved_GBs": (b2 / l2) / (ms2 / l2 * 1e-3) / 1e9}
+    if not args.no_path:
+        out["lambda_path"] = lambda_path(tk, torch, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))
