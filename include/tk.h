@@ -121,6 +121,24 @@ int tk_hvp(const void *d_K, int dtype, int64_t n, int m, const double *d_alpha,
            const double *d_v, int64_t B, double *d_h, double *d_g, int acc, void *d_work,
            size_t work_bytes, void *stream);
 
+/*
+ * Autotuner of the vector tile: the number of alpha vectors (and directions)
+ * that share one read of the packed tensor inside a workgroup, for
+ * tk_contract (d_v == NULL) or tk_hvp with B vectors and accumulation `acc`.
+ * Times tiles 1, 2 and 4 (those the accumulation mode has: FP32 1/2/4, plain
+ * FP64 1/2/4 for contractions and 1/2 for directional derivatives,
+ * compensated 1) on this tensor and these inputs, keeps the fastest for the
+ * current device and shape (later tk_contract / tk_hvp / tk_solve_dual calls
+ * of that shape use it) and returns it in *h_tile.  h_ms (optional, host, 3
+ * entries) receives milliseconds per call for tiles 1, 2, 4 (-1 where not
+ * timed).  d_alpha, d_v: [B*n] device inputs; d_out [B*n] device scratch for
+ * the results; d_work sized by tk_contract_workspace.  Synchronises.
+ * Errors: as tk_contract.
+ */
+int tk_autotune(const void *d_K, int dtype, int64_t n, int m, const double *d_alpha,
+                const double *d_v, int64_t B, int acc, double *d_out, void *d_work,
+                size_t work_bytes, void *stream, int *h_tile, double *h_ms);
+
 /* Options of the dual solve (host struct). */
 typedef struct {
     int max_newton;      /* Newton iterations per lambda (default 100) */

@@ -141,6 +141,22 @@ def solve_workspace(n: int, m: int, B: int, dtype) -> int:
     return out.value
 
 
+def autotune(K: PackedTensor, alpha: torch.Tensor, v: Optional[torch.Tensor] = None, acc: int = ACC_AUTO):
+    """Pick (and remember for this device and shape) the vector tile of
+    contract (v None) or hvp with these B vectors.  Returns (tile, {tile: ms},
+    out) where out holds the results of the last tile timed (the largest)."""
+    a2 = _dev_f64(alpha, "alpha").reshape(-1, K.n)
+    B = a2.shape[0]
+    v2 = None if v is None else _dev_f64(v, "v").reshape(B, K.n)
+    out = torch.empty(B, K.n, dtype=torch.float64, device=a2.device)
+    work = _workspace(contract_workspace(K.n, K.m, B, K.dtype), a2.device)
+    tile = ctypes.c_int()
+    ms = (ctypes.c_double * 3)()
+    _lib.check(_lib.load().tk_autotune(_ptr(K.data), K.dtype, K.n, K.m, _ptr(a2), _ptr(v2), B, acc, _ptr(out),
+                                       _ptr(work), work.numel(), _stream(), ctypes.byref(tile), ms))
+    return tile.value, {t: ms[i] for i, t in enumerate((1, 2, 4)) if ms[i] >= 0}, out
+
+
 def solve_dual(K: PackedTensor, y: torch.Tensor, lambdas: Sequence[float], tol: float = 1e-11,
                max_newton: int = 100, max_cg: int = 2000, fixed_iters: int = 0,
                alpha0: Optional[torch.Tensor] = None, polish: Optional[PackedTensor] = None,

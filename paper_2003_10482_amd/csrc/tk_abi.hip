@@ -5,7 +5,9 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "tk_common.hpp"
@@ -59,6 +61,7 @@ struct PassPlan {
     int q;
     int64_t count, units;
     int groups;
+    int bt;                    // vectors per tile
     size_t s_off, s_bytes;     // order q-2 output (and its tangent right after when hv)
     size_t p_off, p_bytes;     // partials (and tangent partials right after)
 };
@@ -79,9 +82,41 @@ int pass_in_kind(int i, int dtype, int mode)
     return mode == ACC_DD ? 3 : mode == ACC_PLAIN64 ? 0 : 1;
 }
 int pass_hv(int i, bool hv) { return hv ? (i == 0 ? 1 : 2) : 0; }
-int pass_bt(int i, int mode, int64_t B) { return (i == 0 && mode == ACC_PLAIN32 && B >= 4) ? 4 : 1; }
 
-ContractPlan make_plan(int64_t n, int m, int64_t B, int mode, bool hv, int dtype)
+// Vector tile of the first pass: the autotuner's choice for this device and
+// shape when it has run, else 4 vectors per tile with FP32 arithmetic and 1
+// otherwise.  Later passes read per-vector arrays: always 1.
+struct TileKey {
+    int dev, dtype, mode, hv, m;
+    int64_t n, B;
+    bool operator<(const TileKey &o) const
+    {
+        return std::tie(dev, dtype, mode, hv, m, n, B) < std::tie(o.dev, o.dtype, o.mode, o.hv, o.m, o.n, o.B);
+    }
+};
+std::mutex g_tile_mu;
+std::map<TileKey, int> g_tiles;
+
+int tile_limit(int mode, bool hv)
+{
+    if (mode == ACC_PLAIN32) return 4;
+    if (mode == ACC_PLAIN64) return hv ? 2 : 4;
+    return 1;
+}
+
+int pass_bt(int i, int mode, int64_t B, int64_t n, int m, int dtype, bool hv, int force)
+{
+    if (i != 0 || B < 2) return 1;
+    if (force > 0) return force < tile_limit(mode, hv) ? force : tile_limit(mode, hv);
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    auto it = g_tiles.find(TileKey{dev, dtype, mode, hv ? 1 : 0, m, n, B});
+    if (it != g_tiles.end()) return it->second;
+    return (mode == ACC_PLAIN32 && B >= 4) ? 4 : 1;
+}
+
+ContractPlan make_plan(int64_t n, int m, int64_t B, int mode, bool hv, int dtype, int force_bt = 0)
 {
     ContractPlan pl;
     size_t off = 0;
@@ -91,7 +126,8 @@ ContractPlan make_plan(int64_t n, int m, int64_t B, int mode, bool hv, int dtype
         p.q = q;
         p.count = packed_count(n, q);
         p.units = q >= 4 ? packed_count(n, q - 2) : 1;
-        const int bt = pass_bt(i, mode, B);
+        const int bt = pass_bt(i, mode, B, n, m, dtype, hv, force_bt);
+        p.bt = bt;
         p.groups = pass_groups(q, n, p.count,
                                q >= 4 ? pass_resident(q, pass_in_kind(i, dtype, mode), mode, pass_hv(i, hv), bt, n)
                                       : 1,
@@ -133,10 +169,11 @@ std::vector<TimedLaunch> g_timing;
 
 // Run every pass of the contraction (and its tangent when vdir != null).
 int run_contract(const void *K, int dtype, int64_t n, int m, const double *alpha, const double *vdir,
-                 int64_t B, double *g, double *h, int mode, void *work, size_t work_bytes, hipStream_t st)
+                 int64_t B, double *g, double *h, int mode, void *work, size_t work_bytes, hipStream_t st,
+                 int force_bt = 0)
 {
     const bool hv = vdir != nullptr;
-    const ContractPlan pl = make_plan(n, m, B, mode, hv, dtype);
+    const ContractPlan pl = make_plan(n, m, B, mode, hv, dtype, force_bt);
     if (work_bytes < pl.bytes || (pl.bytes && !work))
         return fail(TK_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", work_bytes, pl.bytes);
     unsigned char *w = reinterpret_cast<unsigned char *>(work);
@@ -167,7 +204,7 @@ int run_contract(const void *K, int dtype, int64_t n, int m, const double *alpha
         prm.plan = pass_plan(pp.q, n, pp.groups, &perr);
         if (perr || !prm.plan) return fail(TK_EHIP, "could not place the work plan of pass q=%d", pp.q);
         const int hvl = pass_hv(i, hv);
-        const int bt = pass_bt(i, mode, B);
+        const int bt = pp.bt;
         TimedLaunch tl{};
         bool timed = false;
         if (i == 0) {
@@ -220,11 +257,68 @@ size_t contract_ws(int64_t n, int m, int64_t B, int dtype)
     const int modes[3] = {dtype == TK_F64 ? ACC_DD : ACC_PLAIN32, dtype == TK_F64 ? ACC_PLAIN64 : ACC_PLAIN32,
                           ACC_PLAIN32};
     for (int mode : modes)
-        for (int hv = 0; hv < 2; ++hv) {
-            const size_t b = make_plan(n, m, B, mode, hv != 0, dtype).bytes;
-            if (b > w) w = b;
-        }
+        for (int hv = 0; hv < 2; ++hv)
+            for (int t = 1; t <= tile_limit(mode, hv != 0); t *= 2) {
+                const size_t b = make_plan(n, m, B, mode, hv != 0, dtype, t).bytes;
+                if (b > w) w = b;
+            }
     return w;
+}
+
+// Time each vector tile (1, 2, 4 where the mode has it) for B vectors on this
+// tensor and keep the fastest for the device and shape.  alpha/vdir [B][n]
+// are timing inputs, out [B][n] receives results.  ms[t] = time of tile 2^t.
+int autotune_tile(const void *K, int dtype, int64_t n, int m, const double *alpha, const double *vdir, int64_t B,
+                  int mode, double *out, void *work, size_t work_bytes, hipStream_t st, int *tile, double ms[3])
+{
+    const bool hv = vdir != nullptr;
+    for (int t = 0; t < 3; ++t) ms[t] = -1.0;
+    *tile = 1;
+    if (B < 2) return TK_OK;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return fail(TK_EHIP, "event create failed");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return fail(TK_EHIP, "event create failed");
+    }
+    int rc = TK_OK;
+    double best = INFINITY;
+    for (int t = 1, ti = 0; t <= tile_limit(mode, hv) && !rc; t *= 2, ++ti) {
+        for (int rep = 0; rep < 3 && !rc; ++rep) {   // one untimed launch, then two timed
+            if (rep == 1) hipEventRecord(e0, st);
+            rc = run_contract(K, dtype, n, m, alpha, vdir, B, hv ? nullptr : out, hv ? out : nullptr, mode, work,
+                              work_bytes, st, t);
+        }
+        if (rc) break;
+        hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess) {
+            rc = fail(TK_EHIP, "event synchronize failed");
+            break;
+        }
+        float f = 0.f;
+        hipEventElapsedTime(&f, e0, e1);
+        ms[ti] = 0.5 * (double)f;
+        if (ms[ti] < best) {
+            best = ms[ti];
+            *tile = t;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return rc;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    g_tiles[TileKey{dev, dtype, mode, hv ? 1 : 0, m, n, B}] = *tile;
+    return TK_OK;
+}
+
+bool tile_tuned(int dtype, int64_t n, int m, int64_t B, int mode, bool hv)
+{
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    return g_tiles.count(TileKey{dev, dtype, mode, hv ? 1 : 0, m, n, B}) > 0;
 }
 
 }  // namespace
@@ -317,6 +411,27 @@ int tk_hvp(const void *d_K, int dtype, int64_t n, int m, const double *d_alpha, 
     int mode;
     if ((rc = mode_for(dtype, acc, true, &mode))) return rc;
     return run_contract(d_K, dtype, n, m, d_alpha, d_v, B, d_g, d_h, mode, d_work, work_bytes, as_stream(stream));
+}
+
+int tk_autotune(const void *d_K, int dtype, int64_t n, int m, const double *d_alpha, const double *d_v, int64_t B,
+                int acc, double *d_out, void *d_work, size_t work_bytes, void *stream, int *h_tile, double *h_ms)
+{
+    int rc;
+    if ((rc = check_nm(n, m))) return rc;
+    if ((rc = check_dtype(dtype))) return rc;
+    if (B < 1) return fail(TK_EINVAL, "B must be >= 1");
+    if (!d_K || !d_alpha || !d_out || !h_tile) return fail(TK_EINVAL, "null pointer");
+    int mode;
+    if ((rc = mode_for(dtype, acc, d_v != nullptr, &mode))) return rc;
+    const size_t need = contract_ws(n, m, B, dtype);
+    if (work_bytes < need || (need && !d_work))
+        return fail(TK_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", work_bytes, need);
+    double ms[3];
+    rc = autotune_tile(d_K, dtype, n, m, d_alpha, d_v, B, mode, d_out, d_work, work_bytes, as_stream(stream), h_tile,
+                       ms);
+    if (h_ms)
+        for (int t = 0; t < 3; ++t) h_ms[t] = ms[t];
+    return rc;
 }
 
 int tk_timing_start(void)
@@ -540,13 +655,21 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
         const int dth = (dt != TK_F64 && o.polish_K) ? TK_F64 : dt;
         const int hmode = dth == TK_F64 ? ACC_PLAIN64 : ACC_PLAIN32;
         const int64_t hc = n < kHessChunk ? n : kHessChunk;
+        if (!tile_tuned(dth, n, m, hc, hmode, true)) {   // pick the vector tile of the column blocks once
+            TK_HIP_CHECK(vec_rep_eye(alpha + b * n, sb.hA, sb.hV, 0, hc, n, st));
+            int tile;
+            double ms[3];
+            int rc = autotune_tile(Kh, dth, n, m, sb.hA, sb.hV, hc, hmode, sb.hM, sb.cw, sb.cw_bytes, st, &tile, ms);
+            if (rc) return rc;
+        }
+        const int hbt = pass_bt(0, hmode, hc, n, m, dth, true, 0);
         for (int64_t j0 = 0; j0 < n; j0 += hc) {
             const int64_t k = (n - j0) < hc ? (n - j0) : hc;
             TK_HIP_CHECK(vec_rep_eye(alpha + b * n, sb.hA, sb.hV, j0, k, n, st));
             int rc = run_contract(Kh, dth, n, m, sb.hA, sb.hV, k, nullptr, sb.hM + j0 * n, hmode, sb.cw,
                                   sb.cw_bytes, st);
             if (rc) return rc;
-            hess_passes += (int)(hmode == ACC_PLAIN32 ? (k + 3) / 4 : k);
+            hess_passes += (int)((k + hbt - 1) / hbt);
         }
         Precond &P = pc[b];
         P.J.resize((size_t)n * n);

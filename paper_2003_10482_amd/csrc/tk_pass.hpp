@@ -919,9 +919,13 @@ hipError_t launch_pair(const PairParams &pp, int groups, int btiles, hipStream_t
 template <int Q, int NB, typename TIn, int MODE, int HV>
 hipError_t dispatch_bt(const PairParams &pp, int groups, int bt, hipStream_t st)
 {
-    if constexpr (MODE == ACC_PLAIN32) {
+    // vector tiles (several vectors per read of a shared input array): FP32
+    // and plain FP64 accumulation, first pass (a shared tensor) only
+    if constexpr (MODE == ACC_PLAIN32 || (MODE == ACC_PLAIN64 && HV < 2)) {
         if (bt >= 4 && pp.a_stride == 0)
             return launch_pair<Q, NB, TIn, MODE, HV, 4>(pp, groups, (int)((pp.B + 3) / 4), st);
+        if (bt >= 2 && pp.a_stride == 0)
+            return launch_pair<Q, NB, TIn, MODE, HV, 2>(pp, groups, (int)((pp.B + 1) / 2), st);
     }
     (void)bt;
     return launch_pair<Q, NB, TIn, MODE, HV, 1>(pp, groups, (int)pp.B, st);

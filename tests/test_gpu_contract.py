@@ -145,6 +145,32 @@ def test_reduced_precision_relative(n, m, storage):
         assert np.max(np.abs(h[i] - ref)) <= 1e-4 * np.max(np.abs(ref)), (n, m, storage, cols[i])
 
 
+@pytest.mark.parametrize("acc", ["f64", "f32"])
+@pytest.mark.parametrize("hv", [False, True])
+def test_autotuned_tiles(acc, hv):
+    """The autotuner times the vector tiles and keeps one; the largest tile's
+    results (left in the output by the tuner) and the tuned call both match
+    the oracle (plain FP64 / FP32 accumulation bounds)."""
+    n, m, B = 70, 4, 6
+    K = random_symmetric_packed_values(L.packed_count(n, m), seed=91 + int(hv))
+    A = random_alpha(n, seed=92, batch=B)
+    V = random_alpha(n, seed=93, batch=B)
+    if acc == "f64":
+        Kd, Kr = _packed_dev(K, n, m, "f64")
+        a = tk.ACC_F64
+    else:
+        Kd, Kr = _packed_dev(K, n, m, "f32")
+        a = tk.ACC_AUTO
+    tile, ms, out = tk.autotune(Kd, to_dev(A), to_dev(V) if hv else None, acc=a)
+    assert tile in ms and all(t in (1, 2, 4) for t in ms)
+    got = to_np(tk.hvp(Kd, to_dev(A), to_dev(V), acc=a) if hv else tk.contract(Kd, to_dev(A), acc=a))
+    for res in (to_np(out), got):
+        for b in range(B):
+            ref = (T.hvp_packed(Kr, n, m, A[b], V[b]) if hv else T.contract_packed(Kr, n, m, A[b]))
+            tol = 1e-12 if acc == "f64" else 1e-4
+            assert np.max(np.abs(res[b] - ref)) <= tol * np.max(np.abs(ref)), (acc, hv, tile, b)
+
+
 @pytest.mark.parametrize("n,m", [(7, 4), (70, 4), (130, 4), (5, 6), (40, 6), (9, 2)])
 def test_hvp_f64_random_tensor(n, m):
     K = random_symmetric_packed_values(L.packed_count(n, m), seed=n * m + 1)

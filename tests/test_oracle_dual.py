@@ -229,3 +229,22 @@ def test_exact_gradient_and_refinement():
     assert np.abs(g1).max() <= 64 * np.finfo(float).eps * terms.max()
     # the refinement moves the FP64 solution by no more than the FP64 solver's accuracy
     assert np.linalg.norm(a1 - a0) <= 1e-8 * np.linalg.norm(a0)
+
+
+def test_extended_refinement_matches_exact():
+    """The extended-precision refinement reaches the exact-arithmetic
+    refinement's optimum on an exactly representable problem, and cuts the
+    exact gradient of a small-lambda FP64 solve."""
+    assert np.finfo(np.longdouble).nmant >= 63
+    rng = np.random.default_rng(32)
+    n, d, m = 24, 8, 4
+    X = rng.integers(-40, 41, size=(n, d)) / 16.0
+    y = rng.standard_normal(n)
+    for lam in (0.1, 1e-3):
+        a0, _ = D.solve_linear(X, y, lam, m)
+        a_ext = D.refine_linear(X, y, lam, m, a0)
+        a_ex = D.refine_linear_exact(X, y, lam, m, a0)
+        assert np.linalg.norm(a_ext - a_ex) <= 1e-11 * np.linalg.norm(a_ex)
+        g0 = np.abs(D.dual_grad_exact_linear(X, y, lam, m, a0)).max()
+        g1 = np.abs(D.dual_grad_exact_linear(X, y, lam, m, a_ext)).max()
+        assert g1 <= max(g0, 1e-300)
