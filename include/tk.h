@@ -122,6 +122,26 @@ int tk_hvp(const void *d_K, int dtype, int64_t n, int m, const double *d_alpha,
            size_t work_bytes, void *stream);
 
 /*
+ * Workspace bytes needed by tk_hessian for (n, m).
+ */
+int tk_hessian_workspace(int64_t n, int m, size_t *h_bytes);
+
+/*
+ * Hessian of the first dual term, i.e. the Jacobian of the contraction
+ * (Section 4): J = (m-1) K . alpha^{m-2}, the n x n matrix with
+ *   J[i][j] = (m-1) sum_{i_3..i_m} K[i,j,i_3..i_m] alpha[i_3]..alpha[i_m],
+ * so that J v equals tk_hvp's h for every direction v.  One alpha vector
+ * (device, FP64 [n]); d_J receives FP64 [n*n], row-major and symmetric.  The
+ * packed array (any dtype) is read twice (once for m = 2) and the arithmetic
+ * is plain FP64 with a fixed reduction order (bitwise reproducible).  The
+ * dual solve uses it for its preconditioner.  d_work sized by
+ * tk_hessian_workspace.
+ * Errors: TK_EINVAL, TK_ENOMEM (work_bytes too small), TK_EUNSUPPORTED, TK_EHIP.
+ */
+int tk_hessian(const void *d_K, int dtype, int64_t n, int m, const double *d_alpha, double *d_J,
+               void *d_work, size_t work_bytes, void *stream);
+
+/*
  * Autotuner of the vector tile: the number of alpha vectors (and directions)
  * that share one read of the packed tensor inside a workgroup, for
  * tk_contract (d_v == NULL) or tk_hvp with B vectors and accumulation `acc`.

@@ -66,6 +66,8 @@ _SIGNATURES = {
     "tk_contract_workspace": (c_int, [c_i64, c_int, c_i64, c_int, ctypes.POINTER(c_sz)]),
     "tk_contract": (c_int, [c_vp, c_int, c_i64, c_int, c_vp, c_i64, c_vp, c_int, c_vp, c_sz, c_vp]),
     "tk_hvp": (c_int, [c_vp, c_int, c_i64, c_int, c_vp, c_vp, c_i64, c_vp, c_vp, c_int, c_vp, c_sz, c_vp]),
+    "tk_hessian_workspace": (c_int, [c_i64, c_int, ctypes.POINTER(c_sz)]),
+    "tk_hessian": (c_int, [c_vp, c_int, c_i64, c_int, c_vp, c_vp, c_vp, c_sz, c_vp]),
     "tk_autotune": (c_int, [c_vp, c_int, c_i64, c_int, c_vp, c_vp, c_i64, c_int, c_vp, c_vp, c_sz, c_vp,
                             ctypes.POINTER(c_int), ctypes.POINTER(c_dbl)]),
     "tk_solve_opts_default": (None, [ctypes.POINTER(SolveOpts)]),

@@ -135,6 +135,24 @@ def hvp(K: PackedTensor, alpha: torch.Tensor, v: torch.Tensor, with_g: bool = Fa
     return h.reshape(alpha.shape)
 
 
+def hessian_workspace(n: int, m: int) -> int:
+    out = ctypes.c_size_t()
+    _lib.check(_lib.load().tk_hessian_workspace(n, m, ctypes.byref(out)))
+    return out.value
+
+
+def hessian(K: PackedTensor, alpha: torch.Tensor, work: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """J = (m-1) K . alpha^{m-2}, the n x n Jacobian of the contraction (J v
+    equals hvp(K, alpha, v)), in two reads of the packed tensor."""
+    a = _dev_f64(alpha, "alpha").reshape(K.n)
+    J = torch.empty(K.n, K.n, dtype=torch.float64, device=a.device)
+    if work is None:
+        work = _workspace(hessian_workspace(K.n, K.m), a.device)
+    _lib.check(_lib.load().tk_hessian(_ptr(K.data), K.dtype, K.n, K.m, _ptr(a), _ptr(J), _ptr(work), work.numel(),
+                                      _stream()))
+    return J
+
+
 def solve_workspace(n: int, m: int, B: int, dtype) -> int:
     out = ctypes.c_size_t()
     _lib.check(_lib.load().tk_solve_workspace(n, m, B, _DTYPES[dtype], ctypes.byref(out)))

@@ -17,7 +17,7 @@ OUT = os.path.join(HERE, "libtk.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 ARCH = os.environ.get("TK_OFFLOAD_ARCH", "gfx950")
 SOURCES = ["tk_pass_dd.hip", "tk_pass_f64.hip", "tk_pass_f32.hip", "tk_contract.hip", "tk_build.hip",
-           "tk_dense.hip", "tk_vec.hip", "tk_abi.hip"]
+           "tk_dense.hip", "tk_vec.hip", "tk_hess.hip", "tk_abi.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result", "-munsafe-fp-atomics", "-ffp-contract=off"]

@@ -13,6 +13,7 @@
 #include "tk_common.hpp"
 #include "tk_contract.hpp"
 #include "tk_dense.hpp"
+#include "tk_hess.hpp"
 #include "tk_vec.hpp"
 
 namespace tk {
@@ -313,14 +314,6 @@ int autotune_tile(const void *K, int dtype, int64_t n, int m, const double *alph
     return TK_OK;
 }
 
-bool tile_tuned(int dtype, int64_t n, int m, int64_t B, int mode, bool hv)
-{
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    std::lock_guard<std::mutex> lk(g_tile_mu);
-    return g_tiles.count(TileKey{dev, dtype, mode, hv ? 1 : 0, m, n, B}) > 0;
-}
-
 }  // namespace
 }  // namespace tk
 
@@ -413,6 +406,25 @@ int tk_hvp(const void *d_K, int dtype, int64_t n, int m, const double *d_alpha, 
     return run_contract(d_K, dtype, n, m, d_alpha, d_v, B, d_g, d_h, mode, d_work, work_bytes, as_stream(stream));
 }
 
+int tk_hessian_workspace(int64_t n, int m, size_t *h_bytes)
+{
+    int rc;
+    if ((rc = check_nm(n, m))) return rc;
+    if (!h_bytes) return fail(TK_EINVAL, "null output pointer");
+    *h_bytes = hessian_ws(n, m);
+    return TK_OK;
+}
+
+int tk_hessian(const void *d_K, int dtype, int64_t n, int m, const double *d_alpha, double *d_J, void *d_work,
+               size_t work_bytes, void *stream)
+{
+    int rc;
+    if ((rc = check_nm(n, m))) return rc;
+    if ((rc = check_dtype(dtype))) return rc;
+    if (!d_K || !d_alpha || !d_J || !d_work) return fail(TK_EINVAL, "null device pointer");
+    return run_hessian(d_K, dtype, n, m, d_alpha, d_J, d_work, work_bytes, as_stream(stream), nullptr);
+}
+
 int tk_autotune(const void *d_K, int dtype, int64_t n, int m, const double *d_alpha, const double *d_v, int64_t B,
                 int acc, double *d_out, void *d_work, size_t work_bytes, void *stream, int *h_tile, double *h_ms)
 {
@@ -493,12 +505,12 @@ namespace {
 struct SolveBuffers {
     double *g, *grad, *x, *r, *dv, *hd, *at, *gt, *z, *stats, *stats2;
     double *P;             // [B][n][n] preconditioners (inverse Hessians)
-    double *hA, *hV, *hM;  // Hessian assembly: direction blocks [kHessChunk][n] and the matrix [n][n]
+    double *hM;            // assembled Hessian [n][n]
+    unsigned char *hw;     // Hessian kernel workspace
+    size_t hw_bytes;
     unsigned char *cw;
     size_t cw_bytes;
 };
-
-constexpr int64_t kHessChunk = 64;   // Hessian columns per batched directional-derivative launch
 
 size_t solve_ws(int64_t n, int m, int64_t B, int dtype)
 {
@@ -506,16 +518,11 @@ size_t solve_ws(int64_t n, int m, int64_t B, int dtype)
     size_t cw = contract_ws(n, m, B, dtype);
     const size_t cw64 = contract_ws(n, m, B, TK_F64);   // polish passes on an FP64 tensor
     if (cw64 > cw) cw = cw64;
-    const int64_t hc = n < kHessChunk ? n : kHessChunk;
-    size_t cwh = contract_ws(n, m, hc, dtype);          // Hessian blocks
-    const size_t cwh64 = contract_ws(n, m, hc, TK_F64);  // ... on the FP64 polish tensor
-    if (cwh64 > cwh) cwh = cwh64;
-    if (cwh > cw) cw = cwh;
     return 9 * vec + 2 * align256((size_t)B * 8 * sizeof(double)) + align256((size_t)B * n * n * sizeof(double)) +
-           2 * align256((size_t)hc * n * sizeof(double)) + align256((size_t)n * n * sizeof(double)) + cw;
+           align256((size_t)n * n * sizeof(double)) + align256(hessian_ws(n, m)) + cw;
 }
 
-SolveBuffers carve(void *work, int64_t n, int64_t B, size_t total)
+SolveBuffers carve(void *work, int64_t n, int m, int64_t B, size_t total)
 {
     SolveBuffers s{};
     const size_t vec = align256((size_t)B * n * sizeof(double));
@@ -529,13 +536,11 @@ SolveBuffers carve(void *work, int64_t n, int64_t B, size_t total)
     used += align256((size_t)B * 8 * sizeof(double));
     s.P = reinterpret_cast<double *>(w + used);
     used += align256((size_t)B * n * n * sizeof(double));
-    const int64_t hc = n < kHessChunk ? n : kHessChunk;
-    s.hA = reinterpret_cast<double *>(w + used);
-    used += align256((size_t)hc * n * sizeof(double));
-    s.hV = reinterpret_cast<double *>(w + used);
-    used += align256((size_t)hc * n * sizeof(double));
     s.hM = reinterpret_cast<double *>(w + used);
     used += align256((size_t)n * n * sizeof(double));
+    s.hw = w + used;
+    s.hw_bytes = align256(hessian_ws(n, m));
+    used += s.hw_bytes;
     s.cw = w + used;
     s.cw_bytes = total - used;
     return s;
@@ -645,41 +650,22 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
         return sync_copy(out.data(), sb.stats, B * 4);
     };
 
-    // Hessian of problem b at its current alpha into pc[b].J: directional
-    // derivatives along e_0..e_{n-1}.  At the dual optimum the products behind
-    // J cancel by orders of magnitude (alpha is large where X^T alpha is not),
-    // so they run in FP64 on an FP64 tensor (the polish tensor when the solve
-    // runs on reduced storage); FP32 only when no FP64 tensor exists.
+    // Hessian of problem b at its current alpha into pc[b].J (two reads of
+    // the tensor).  At the dual optimum the products behind J cancel by
+    // orders of magnitude (alpha is large where X^T alpha is not), so they run
+    // in FP64 on an FP64 tensor: the polish tensor when the solve runs on
+    // reduced storage, else the reduced tensor itself.
     auto assemble = [&](const void *Kp, int dt, int64_t b) -> int {
         const void *Kh = (dt != TK_F64 && o.polish_K) ? o.polish_K : Kp;
         const int dth = (dt != TK_F64 && o.polish_K) ? TK_F64 : dt;
-        const int hmode = dth == TK_F64 ? ACC_PLAIN64 : ACC_PLAIN32;
-        const int64_t hc = n < kHessChunk ? n : kHessChunk;
-        if (!tile_tuned(dth, n, m, hc, hmode, true)) {   // pick the vector tile of the column blocks once
-            TK_HIP_CHECK(vec_rep_eye(alpha + b * n, sb.hA, sb.hV, 0, hc, n, st));
-            int tile;
-            double ms[3];
-            int rc = autotune_tile(Kh, dth, n, m, sb.hA, sb.hV, hc, hmode, sb.hM, sb.cw, sb.cw_bytes, st, &tile, ms);
-            if (rc) return rc;
-        }
-        const int hbt = pass_bt(0, hmode, hc, n, m, dth, true, 0);
-        for (int64_t j0 = 0; j0 < n; j0 += hc) {
-            const int64_t k = (n - j0) < hc ? (n - j0) : hc;
-            TK_HIP_CHECK(vec_rep_eye(alpha + b * n, sb.hA, sb.hV, j0, k, n, st));
-            int rc = run_contract(Kh, dth, n, m, sb.hA, sb.hV, k, nullptr, sb.hM + j0 * n, hmode, sb.cw,
-                                  sb.cw_bytes, st);
-            if (rc) return rc;
-            hess_passes += (int)((k + hbt - 1) / hbt);
-        }
+        int hp = 0;
+        int rc = run_hessian(Kh, dth, n, m, alpha + b * n, sb.hM, sb.hw, sb.hw_bytes, st, &hp);
+        if (rc) return rc;
+        hess_passes += hp;
         Precond &P = pc[b];
         P.J.resize((size_t)n * n);
         TK_HIP_CHECK(hipMemcpyAsync(P.J.data(), sb.hM, (size_t)n * n * sizeof(double), hipMemcpyDeviceToHost, st));
         TK_HIP_CHECK(hipStreamSynchronize(st));
-        for (int64_t i = 0; i < n; ++i)   // FP32 sums are not exactly symmetric
-            for (int64_t j = 0; j < i; ++j) {
-                const double v = 0.5 * (P.J[i * n + j] + P.J[j * n + i]);
-                P.J[i * n + j] = P.J[j * n + i] = v;
-            }
         P.have = true;
         P.fresh = true;
         return TK_OK;
@@ -999,7 +985,7 @@ int tk_solve_dual(const void *d_K, int dtype, int64_t n, int m, const double *d_
         std::stable_sort(order.begin(), order.end(),
                          [&](int64_t u, int64_t v) { return h_lambdas[u] > h_lambdas[v]; });
         std::vector<Precond> pc(1);
-        SolveBuffers sb = carve(d_work, n, 1, work_bytes);
+        SolveBuffers sb = carve(d_work, n, m, 1, work_bytes);
         int64_t prev = -1;
         for (int64_t idx = 0; idx < B; ++idx) {
             const int64_t b = order[idx];
@@ -1018,7 +1004,7 @@ int tk_solve_dual(const void *d_K, int dtype, int64_t n, int m, const double *d_
             const int64_t nb = (B - b0) < kMaxCoefs ? (B - b0) : kMaxCoefs;
             double *a = d_alpha + b0 * n;
             if (!o.warm_start) TK_HIP_CHECK(hipMemsetAsync(a, 0, (size_t)nb * n * sizeof(double), st));
-            SolveBuffers sb = carve(d_work, n, nb, work_bytes);
+            SolveBuffers sb = carve(d_work, n, m, nb, work_bytes);
             std::vector<Precond> pc(nb);
             rc = solve_batch(d_K, dtype, n, m, d_y, h_lambdas + b0, nb, o, a, h_info + b0, sb, st, pc);
             if (rc != TK_OK && rc != TK_ENOCONV && rc != TK_ENAN) return rc;

@@ -172,18 +172,6 @@ __global__ void __launch_bounds__(256) precond_kernel(const double *__restrict__
     if (threadIdx.x == 0) out[b] = t.hi + t.lo;
 }
 
-// Directions of a Hessian block: A[i] = alpha (k copies), V[i] = e_{j0+i}.
-__global__ void __launch_bounds__(256) rep_eye_kernel(const double *__restrict__ alpha, double *__restrict__ A,
-                                                      double *__restrict__ V, int j0, int k, int n)
-{
-    const int64_t total = (int64_t)k * n;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-        const int i = (int)(t / n), j = (int)(t % n);
-        A[t] = alpha[j];
-        V[t] = (j == j0 + i) ? 1.0 : 0.0;
-    }
-}
-
 }  // namespace
 
 hipError_t vec_grad(const double *g, const double *alpha, const double *y, const Coefs &lam,
@@ -241,13 +229,5 @@ hipError_t vec_precond(const double *P, const double *r, double *z, double *out,
     return hipGetLastError();
 }
 
-hipError_t vec_rep_eye(const double *alpha, double *A, double *V, int64_t j0, int64_t k, int64_t n, hipStream_t st)
-{
-    const int64_t total = k * n;
-    const int blocks = (int)((total + 255) / 256 < 1024 ? (total + 255) / 256 : 1024);
-    hipLaunchKernelGGL(rep_eye_kernel, dim3(blocks < 1 ? 1 : blocks), dim3(256), 0, st, alpha, A, V, (int)j0, (int)k,
-                       (int)n);
-    return hipGetLastError();
-}
 
 }  // namespace tk

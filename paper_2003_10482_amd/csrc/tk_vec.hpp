@@ -28,7 +28,5 @@ hipError_t vec_nonfinite(const double *x, int64_t len, int *flag, hipStream_t st
 // z_b = P_b r_b (P_b symmetric [n][n], n <= 256) and out_b = r_b . z_b
 hipError_t vec_precond(const double *P, const double *r, double *z, double *out, int64_t B, int64_t n,
                        hipStream_t st);
-// A[i] = alpha, V[i] = e_{j0+i} for i < k (directions of a block of Hessian columns)
-hipError_t vec_rep_eye(const double *alpha, double *A, double *V, int64_t j0, int64_t k, int64_t n, hipStream_t st);
 
 }  // namespace tk
