@@ -3,18 +3,18 @@
 One step = one pass of the whole hot path on the workload n=256, d=200, m=4,
 lambda=1e-2 (synthetic, Section 5.4 data model, seed 1002), inputs resident in
 HBM: build the packed FP64 tensor (C(259,4) = 183,181,376 entries, 1.47 GB),
-solve the dual to ||grad D|| <= 1e-11 lambda ||alpha|| with the
-Hessian-preconditioned truncated-Newton solver (every gradient, CG,
-line-search and Hessian-column step streams the packed tensor), recover
-w = (X^T alpha)^3, take the 2-std support and predict on X.  After the timed
-steps, the 64-value lambda path of the same data is solved and timed
-separately ("lambda_path").
+solve the dual to ||grad D|| <= 1e-11 lambda ||alpha|| with the Newton solver
+(compensated gradient and line-search passes over the packed tensor; the
+Hessian assembled in two passes at every Newton step, CG on the dense
+system), recover w = (X^T alpha)^3, take the 2-std support and predict on X.
+After the timed steps, the 64-value lambda path of the same data is solved
+and timed separately ("lambda_path").
 
 value = passes over the packed tensor per second across the timed steps
-        (K . alpha^{m-1} contractions and their directional derivatives).
-roofline = the dominant kernel (the pass that streams K inside the directional
-        derivative), timed with HIP events on its launch stream over the timed
-        region: algorithmic bytes = C x 8 B per launch.
+        (contractions, and the two streaming passes of each Hessian).
+roofline = the kernel with the most time in the timed steps, timed with HIP
+        events on its launch stream: algorithmic bytes = C x 8 B per read of
+        the tensor; "kernels" lists every streaming kernel the same way.
 cpu_baseline = the CPU oracle's packed FP64 contraction (single thread) on a
         seeded random symmetric tensor of the same size.
 
@@ -32,34 +32,47 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_hvp_n256_m4_f64.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2003_10482_amd", "csrc", "tk_pass.hpp")
+CSRC = os.path.join(ROOT, "paper_2003_10482_amd", "csrc")
+# timing kind -> (kernel, its source file, committed counter summary)
+KERNELS = {
+    "contract": ("pair_kernel<4,4,double,0,0,1,8>: contraction pass, compensated FP64",
+                 "tk_pass.hpp", "traffic_contract_dd_n256_m4_f64.json"),
+    "hvp": ("pair_kernel<4,4,double,1,1,1,8>: directional-derivative pass, plain FP64",
+            "tk_pass.hpp", "traffic_hvp_n256_m4_f64.json"),
+    "contract_plain": ("pair_kernel<4,4,double,1,0,*,8>: contraction pass, plain FP64",
+                       "tk_pass.hpp", "traffic_contract_plain_n256_m4_f64.json"),
+    "hessian_tiles": ("hess_tri_kernel<2,double>: Hessian tile sums", "tk_hess.hip",
+                      "traffic_hess_tri_n256_m4_f64.json"),
+    "hessian_units": ("hess_unit_kernel<2,double>: Hessian unit vectors", "tk_hess.hip",
+                      "traffic_hess_unit_n256_m4_f64.json"),
+}
 
 
-def source_digest() -> str:
+def source_digest(src: str) -> str:
     import hashlib
-    with open(KERNEL_SOURCE, "rb") as f:
+    with open(os.path.join(CSRC, src), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the dominant pass from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE runs, or None when the kernel source has changed
-    since they were taken."""
+def measured_traffic(kind: str):
+    """HBM bytes per read of the tensor by kernel `kind` from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE runs, or None when there are none or the
+    kernel source has changed since they were taken."""
+    _, src, fname = KERNELS[kind]
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(os.path.join(ROOT, "profiles", fname)) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("source_sha256_16") != source_digest():
+    if t.get("source_sha256_16") != source_digest(src):
         return None
     return float(t["fetch_bytes_per_launch"]) + float(t["write_bytes_per_launch"])
 
 
-def pass_only(count: int) -> int:
-    """The dominant kernel alone, for counter runs: `count` directional-derivative
-    passes over the FP64 tensor of the benchmark workload (same launch shape as
-    in the solve), then one 1 GiB device-to-device copy whose counters give the
+def pass_only(count: int, kind: str) -> int:
+    """One kernel alone, for counter runs: `count` launches of kernel `kind`
+    over the FP64 tensor of the benchmark workload (same launch shape as in
+    the solve), then one 1 GiB device-to-device copy whose counters give the
     scale of FETCH_SIZE and WRITE_SIZE."""
     import torch
 
@@ -74,12 +87,19 @@ def pass_only(count: int) -> int:
     a = torch.randn(1, wl.n, generator=g, dtype=torch.float64).to(dev)
     v = torch.randn(1, wl.n, generator=g, dtype=torch.float64).to(dev)
     for _ in range(count):
-        tk.hvp(K, a, v)
+        if kind == "hvp":
+            tk.hvp(K, a, v)
+        elif kind == "contract":
+            tk.contract(K, a, acc=tk.ACC_COMPENSATED)
+        elif kind == "contract_plain":
+            tk.contract(K, a, acc=tk.ACC_F64)
+        else:   # both Hessian kernels run in one call
+            tk.hessian(K, a[0])
     src = torch.ones(2 ** 27, dtype=torch.float64, device=dev)
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
-    print(json.dumps({"pass_only": count, "packed_bytes": K.count * 8, "copy_bytes": 2 ** 30}))
+    print(json.dumps({"pass_only": count, "kind": kind, "packed_bytes": K.count * 8, "copy_bytes": 2 ** 30}))
     return 0
 
 
@@ -148,14 +168,15 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-path", action="store_true", help="skip the 64-lambda path (outside the timed steps)")
     ap.add_argument("--pass-only", type=int, default=0,
-                    help="run only this many passes of the dominant kernel (for counter runs)")
+                    help="run only this many launches of one kernel (for counter runs)")
+    ap.add_argument("--pass-kind", default="hvp", choices=sorted(KERNELS))
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path", file=sys.stderr)
         return 2
 
     if args.pass_only:
-        return pass_only(args.pass_only)
+        return pass_only(args.pass_only, args.pass_kind)
 
     import numpy as np
     import torch
@@ -192,10 +213,12 @@ def main() -> int:
     timing = tk.timing_stop()
     ms_step = 1e3 * elapsed / args.steps
 
-    kind = max(timing, key=lambda k: timing[k][1])
-    launches, kms, kbytes = timing[kind]
-    avg_ms = kms / max(launches, 1)
-    achieved = (kbytes / max(launches, 1)) / (avg_ms * 1e-3) / 1e9
+    ran = {k: v for k, v in timing.items() if v[0]}
+    kind = max(ran, key=lambda k: ran[k][1])   # the kernel with the most time in the timed steps
+    launches, kms, kbytes = ran[kind]
+    avg_ms = kms / launches
+    achieved = (kbytes / launches) / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(kind)
     mask_np = mask.cpu().numpy()[0].astype(bool)
     sel = set(np.flatnonzero(mask_np).tolist())
     true = set(wl.support.tolist())
@@ -224,18 +247,14 @@ def main() -> int:
                   "status": infos[0]["status"], "support_f1": f1, "support_size": len(sel)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     # counters are per read of the tensor; launches here average
-                     # kbytes / launches / (C * 8) reads
-                     "traffic": (measured_traffic() * (kbytes / max(launches, 1)) / (count * 8.0)
-                                 if kind == "hvp" and measured_traffic() is not None else None),
-                     "kernel": f"packed-tensor pass ({kind})", "avg_launch_ms": avg_ms,
-                     "launches": launches},
+                     # counters are per read of the tensor; a launch reads it
+                     # kbytes / launches / (C * 8) times
+                     "traffic": (traffic * (kbytes / launches) / (count * 8.0) if traffic is not None else None),
+                     "kernel": KERNELS[kind][0], "avg_launch_ms": avg_ms, "launches": launches,
+                     "kernels": {k: {"launches": l, "total_ms": ms, "avg_launch_ms": ms / l,
+                                     "achieved_GBs": (b / l) / (ms / l * 1e-3) / 1e9}
+                                 for k, (l, ms, b) in ran.items()}},
     }
-    other = "contract" if kind == "hvp" else "hvp"
-    if timing[other][0]:
-        l2, ms2, b2 = timing[other]
-        out["roofline"]["other_pass"] = {"kind": other, "avg_launch_ms": ms2 / l2,
-                                         "achieved_GBs": (b2 / l2) / (ms2 / l2 * 1e-3) / 1e9}
     if not args.no_path:
         out["lambda_path"] = lambda_path(tk, torch, dev)
     if not args.no_cpu_baseline:

@@ -172,27 +172,32 @@ typedef struct {
                             compensated gradients until tol is met (may be NULL) */
     int polish_dtype;    /* dtype of polish_K (must be TK_F64 when set) */
     int verbose;         /* print one line per Newton iteration to stderr */
-    int precond;         /* 1 (default): CG preconditioned with (J + lambda I)^{-1}, J the
-                            Hessian of the contraction assembled from n directional
-                            derivatives (FP64 on the FP64 tensor or polish tensor) and
-                            inverted on the host (n <= 256); 0: plain CG */
-    int precond_refresh; /* re-assemble J after a Newton step that needed more than this
-                            many CG steps (default 12) */
+    int precond;         /* 1 (default): at every Newton step J, the Hessian of the
+                            contraction, is assembled by tk_hessian (FP64, on the FP64
+                            tensor or the polish tensor) and CG runs on the dense system
+                            (J + lambda I) p = -grad, preconditioned with an inverse
+                            (J' + lambda' I)^{-1} factored on the host from an earlier
+                            Hessian; 0: unpreconditioned CG whose products are tk_hvp
+                            passes over the tensor */
+    int precond_refresh; /* refactor the inverse after a Newton step that needed more than
+                            this many CG steps (default 25) */
     int continuation;    /* B > 1: 1 (default) solves the lambdas one after another from the
                             largest down, each started from the previous solution and keeping
-                            its J; 0: all lambdas in lock step, sharing every pass */
+                            its preconditioner; 0: all lambdas in lock step, sharing every
+                            pass */
 } tk_solve_opts;
 
 typedef struct {
     int newton_iters;
     int cg_iters;
-    int passes;          /* passes over the packed tensor (contractions + HVPs) */
+    int passes;          /* passes over the packed tensor outside Hessian assembly
+                            (contractions, and HVPs when precond = 0) */
     double grad_norm;    /* final ||grad D||_2 (compensated FP64 when polished or FP64 storage) */
     double objective;    /* final D(alpha) */
     double alpha_norm;
     int status;          /* TK_OK or TK_ENOCONV / TK_ENAN for this lambda */
-    int hess_passes;     /* passes over the packed tensor spent on Hessian assembly (one per
-                            tile of 4 directions) */
+    int hess_passes;     /* passes over the packed tensor spent on Hessian assembly (two per
+                            Hessian, one for m = 2) */
     int precond_updates; /* preconditioner factorisations for this lambda */
 } tk_solve_info;
 
@@ -204,8 +209,8 @@ int tk_solve_workspace(int64_t n, int m, int64_t B, int dtype, size_t *h_bytes);
  * Minimise the dual D(alpha) of eq. dual_tensor_kernel for B regularisation
  * values (a lambda path), by truncated Newton: each Newton step solves
  * (J(alpha) + lambda I) p = -grad D with preconditioned conjugate gradients
- * whose products are tk_hvp passes, followed by an Armijo backtracking line
- * search on D.  With opts->continuation the lambdas are solved in decreasing
+ * on the assembled Hessian (tk_hessian; tk_hvp passes when opts->precond is
+ * 0), followed by an Armijo backtracking line search on D.  With opts->continuation the lambdas are solved in decreasing
  * order from each other's solutions; otherwise all B share every pass.  d_y is the FP64 response [n]; h_lambdas
  * holds B values (host); d_alpha [B*n] receives the solutions (and holds the
  * warm start when opts->warm_start).  h_info receives B records.
@@ -274,14 +279,18 @@ int tk_dmse_dlambda(const void *d_K, int dtype, int64_t n, int m, const double *
 int tk_dmse_workspace(int64_t n, int m, int64_t d, int64_t nval, int dtype, size_t *h_bytes);
 
 /*
- * Instrumentation (not part of the method): while enabled, every pass that
- * streams the packed tensor (the first pass of tk_contract / tk_hvp, also when
- * called inside tk_solve_dual or tk_dmse_dlambda) is bracketed by HIP events on
- * its own stream.  tk_timing_stop synchronises those events and returns, per
- * kind (0 = contraction, 1 = directional derivative), the number of launches,
- * their summed duration in milliseconds and the bytes of the packed tensor they
- * read (entries x storage size).  Arrays are host arrays of length 2.
+ * Instrumentation (not part of the method): while enabled, every kernel that
+ * streams the packed tensor (the first pass of tk_contract / tk_hvp and the two
+ * streaming kernels of tk_hessian, also inside tk_solve_dual or
+ * tk_dmse_dlambda) is bracketed by HIP events on its own stream.
+ * tk_timing_stop synchronises those events and returns, per kind (0 =
+ * contraction with compensated accumulation, 1 = directional derivative, 2 =
+ * contraction with plain accumulation, 3 = Hessian tile sums, 4 = Hessian unit
+ * vectors), the number of launches, their summed duration in milliseconds and
+ * the bytes of the packed tensor they read (entries x storage size per read).
+ * Arrays are host arrays of length TK_TIMING_KINDS.
  */
+#define TK_TIMING_KINDS 5
 int tk_timing_start(void);
 int tk_timing_stop(int64_t *h_launches, double *h_ms, double *h_bytes);
 

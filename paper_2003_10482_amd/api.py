@@ -179,9 +179,10 @@ def solve_dual(K: PackedTensor, y: torch.Tensor, lambdas: Sequence[float], tol: 
                max_newton: int = 100, max_cg: int = 2000, fixed_iters: int = 0,
                alpha0: Optional[torch.Tensor] = None, polish: Optional[PackedTensor] = None,
                verbose: bool = False, raise_on_noconv: bool = False, precond: bool = True,
-               precond_refresh: int = 12, continuation: bool = True):
+               precond_refresh: int = 25, continuation: bool = True):
     """Dual solve for every lambda.  Returns (alpha [B, n], list of info dicts).
-    precond: Hessian-preconditioned CG; continuation: lambdas solved from the
+    precond: Newton systems on the assembled Hessian with an inverse
+    preconditioner (else unpreconditioned CG on tensor passes); continuation: lambdas solved from the
     largest down, each from the previous solution (else in lock step)."""
     y = _dev_f64(y, "y")
     lams = [float(x) for x in lambdas]
@@ -312,10 +313,16 @@ def timing_start() -> None:
     _lib.check(_lib.load().tk_timing_start())
 
 
+TIMING_KINDS = ("contract", "hvp", "contract_plain", "hessian_tiles", "hessian_units")
+
+
 def timing_stop() -> dict:
-    """Stop and return {kind: (launches, total_ms, bytes)} for kind in contract/hvp."""
-    n = (ctypes.c_int64 * 2)()
-    ms = (ctypes.c_double * 2)()
-    by = (ctypes.c_double * 2)()
+    """Stop and return {kind: (launches, total_ms, bytes)} for every kind in
+    TIMING_KINDS (compensated contraction, directional derivative, plain
+    contraction, the two streaming kernels of the Hessian)."""
+    k = len(TIMING_KINDS)
+    n = (ctypes.c_int64 * k)()
+    ms = (ctypes.c_double * k)()
+    by = (ctypes.c_double * k)()
     _lib.check(_lib.load().tk_timing_stop(n, ms, by))
-    return {"contract": (n[0], ms[0], by[0]), "hvp": (n[1], ms[1], by[1])}
+    return {name: (n[i], ms[i], by[i]) for i, name in enumerate(TIMING_KINDS)}

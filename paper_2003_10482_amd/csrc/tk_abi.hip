@@ -159,14 +159,35 @@ int mode_for(int dtype, int acc, bool hv, int *mode)
 }
 
 // ------------------------------------------------------- instrumentation ----
-struct TimedLaunch {
-    hipEvent_t a, b;
-    int kind;
-    double bytes;
-};
 std::mutex g_timing_mu;
 bool g_timing_on = false;
 std::vector<TimedLaunch> g_timing;
+
+}  // namespace
+
+TimedLaunch timing_begin(int kind, double bytes, hipStream_t st)
+{
+    TimedLaunch tl{};
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    if (g_timing_on && hipEventCreate(&tl.a) == hipSuccess && hipEventCreate(&tl.b) == hipSuccess) {
+        tl.on = true;
+        tl.kind = kind;
+        tl.bytes = bytes;
+        hipEventRecord(tl.a, st);
+    }
+    return tl;
+}
+
+void timing_end(TimedLaunch &tl, hipStream_t st)
+{
+    if (!tl.on) return;
+    hipEventRecord(tl.b, st);
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    g_timing.push_back(tl);
+    tl.on = false;
+}
+
+namespace {
 
 // Run every pass of the contraction (and its tangent when vdir != null).
 int run_contract(const void *K, int dtype, int64_t n, int m, const double *alpha, const double *vdir,
@@ -207,24 +228,12 @@ int run_contract(const void *K, int dtype, int64_t n, int m, const double *alpha
         const int hvl = pass_hv(i, hv);
         const int bt = pp.bt;
         TimedLaunch tl{};
-        bool timed = false;
-        if (i == 0) {
-            std::lock_guard<std::mutex> lk(g_timing_mu);
-            if (g_timing_on && hipEventCreate(&tl.a) == hipSuccess && hipEventCreate(&tl.b) == hipSuccess) {
-                timed = true;
-                tl.kind = hv ? 1 : 0;
-                // one read of the stored tensor per tile of bt vectors
-                tl.bytes = (double)pp.count * (double)dtype_size(dtype) * (double)((B + bt - 1) / bt);
-                hipEventRecord(tl.a, st);
-            }
-        }
+        if (i == 0)   // one read of the stored tensor per tile of bt vectors
+            tl = timing_begin(hv ? 1 : (mode == ACC_DD ? 0 : 2),
+                              (double)pp.count * (double)dtype_size(dtype) * (double)((B + bt - 1) / bt), st);
         hipError_t e = launch_pass(pp.q, in_kind, mode, hvl, bt, prm, pp.groups, st);
         if (e != hipSuccess) return fail(TK_EHIP, "contraction pass q=%d failed: %s", pp.q, hipGetErrorString(e));
-        if (timed) {
-            hipEventRecord(tl.b, st);
-            std::lock_guard<std::mutex> lk(g_timing_mu);
-            g_timing.push_back(tl);
-        }
+        timing_end(tl, st);
         rv.part[i] = prm.part;
         rv.groups[i] = pp.groups;
         rt.part[i] = prm.part_d;
@@ -463,7 +472,7 @@ int tk_timing_stop(int64_t *h_launches, double *h_ms, double *h_bytes)
     if (!h_launches || !h_ms || !h_bytes) return fail(TK_EINVAL, "null output pointer");
     std::lock_guard<std::mutex> lk(g_timing_mu);
     g_timing_on = false;
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < kTimingKinds; ++k) {
         h_launches[k] = 0;
         h_ms[k] = 0.0;
         h_bytes[k] = 0.0;
@@ -492,7 +501,7 @@ void tk_solve_opts_default(tk_solve_opts *o)
     o->tol = 1e-11;
     o->polish_dtype = TK_F64;
     o->precond = 1;
-    o->precond_refresh = 12;
+    o->precond_refresh = 25;
     o->continuation = 1;
 }
 
@@ -503,9 +512,9 @@ namespace tk {
 namespace {
 
 struct SolveBuffers {
-    double *g, *grad, *x, *r, *dv, *hd, *at, *gt, *z, *stats, *stats2;
+    double *g, *grad, *x, *r, *dv, *hd, *at, *gt, *z, *best, *stats, *stats2;
     double *P;             // [B][n][n] preconditioners (inverse Hessians)
-    double *hM;            // assembled Hessian [n][n]
+    double *Jd;            // [B][n][n] Hessians J at the current iterates
     unsigned char *hw;     // Hessian kernel workspace
     size_t hw_bytes;
     unsigned char *cw;
@@ -518,8 +527,8 @@ size_t solve_ws(int64_t n, int m, int64_t B, int dtype)
     size_t cw = contract_ws(n, m, B, dtype);
     const size_t cw64 = contract_ws(n, m, B, TK_F64);   // polish passes on an FP64 tensor
     if (cw64 > cw) cw = cw64;
-    return 9 * vec + 2 * align256((size_t)B * 8 * sizeof(double)) + align256((size_t)B * n * n * sizeof(double)) +
-           align256((size_t)n * n * sizeof(double)) + align256(hessian_ws(n, m)) + cw;
+    return 10 * vec + 2 * align256((size_t)B * 8 * sizeof(double)) + align256((size_t)B * n * n * sizeof(double)) +
+           align256((size_t)B * n * n * sizeof(double)) + align256(hessian_ws(n, m)) + cw;
 }
 
 SolveBuffers carve(void *work, int64_t n, int m, int64_t B, size_t total)
@@ -527,17 +536,17 @@ SolveBuffers carve(void *work, int64_t n, int m, int64_t B, size_t total)
     SolveBuffers s{};
     const size_t vec = align256((size_t)B * n * sizeof(double));
     unsigned char *w = reinterpret_cast<unsigned char *>(work);
-    double **v[9] = {&s.g, &s.grad, &s.x, &s.r, &s.dv, &s.hd, &s.at, &s.gt, &s.z};
-    for (int i = 0; i < 9; ++i) *v[i] = reinterpret_cast<double *>(w + i * vec);
-    size_t used = 9 * vec;
+    double **v[10] = {&s.g, &s.grad, &s.x, &s.r, &s.dv, &s.hd, &s.at, &s.gt, &s.z, &s.best};
+    for (int i = 0; i < 10; ++i) *v[i] = reinterpret_cast<double *>(w + i * vec);
+    size_t used = 10 * vec;
     s.stats = reinterpret_cast<double *>(w + used);
     used += align256((size_t)B * 8 * sizeof(double));
     s.stats2 = reinterpret_cast<double *>(w + used);
     used += align256((size_t)B * 8 * sizeof(double));
     s.P = reinterpret_cast<double *>(w + used);
     used += align256((size_t)B * n * n * sizeof(double));
-    s.hM = reinterpret_cast<double *>(w + used);
-    used += align256((size_t)n * n * sizeof(double));
+    s.Jd = reinterpret_cast<double *>(w + used);
+    used += align256((size_t)B * n * n * sizeof(double));
     s.hw = w + used;
     s.hw_bytes = align256(hessian_ws(n, m));
     used += s.hw_bytes;
@@ -591,12 +600,12 @@ bool spd_inverse(std::vector<double> &A, int n)
     return true;
 }
 
-// Host copy of the last assembled Hessian J = (m-1) K . alpha^{m-2} of one
-// problem; the preconditioner of a lambda is (J + lambda I)^{-1}.
+// Device slot b of the preconditioner holds an inverse (J' + lambda' I)^{-1}
+// from an earlier iterate (and, along a lambda path, an earlier lambda): a
+// stale inverse still preconditions the current system well.
 struct Precond {
-    bool have = false;      // J holds a matrix
-    bool fresh = false;     // ... assembled at the current problem's iterate history
-    std::vector<double> J;
+    bool dev = false;
+    bool ident = false;   // ... and that inverse is I / lambda' (from J = 0 at alpha = 0)
 };
 
 struct ProblemState {
@@ -605,7 +614,6 @@ struct ProblemState {
     int newton, cg, status;
     int last_cg;       // CG steps of the last Newton step
     bool done;
-    bool pc_ready;     // the device holds this problem's preconditioner
 };
 
 // One batch (B <= kMaxCoefs) of dual solves.  Newton direction from CG on
@@ -650,50 +658,66 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
         return sync_copy(out.data(), sb.stats, B * 4);
     };
 
-    // Hessian of problem b at its current alpha into pc[b].J (two reads of
-    // the tensor).  At the dual optimum the products behind J cancel by
-    // orders of magnitude (alpha is large where X^T alpha is not), so they run
-    // in FP64 on an FP64 tensor: the polish tensor when the solve runs on
-    // reduced storage, else the reduced tensor itself.
-    auto assemble = [&](const void *Kp, int dt, int64_t b) -> int {
+    // Hessian J_b = (m-1) K . alpha_b^{m-2} of problem b at its current alpha
+    // into its device slot (two reads of the tensor); at alpha = 0 it is zero
+    // for m >= 4.  At the dual optimum the products behind J cancel by orders
+    // of magnitude (alpha is large where X^T alpha is not), so they run in
+    // FP64 on an FP64 tensor: the polish tensor when the solve runs on reduced
+    // storage, else the reduced tensor itself.
+    auto assemble = [&](const void *Kp, int dt, int64_t b, bool zero) -> int {
+        double *Jb = sb.Jd + b * n * n;
+        if (zero) {
+            TK_HIP_CHECK(hipMemsetAsync(Jb, 0, (size_t)n * n * sizeof(double), st));
+            return TK_OK;
+        }
         const void *Kh = (dt != TK_F64 && o.polish_K) ? o.polish_K : Kp;
         const int dth = (dt != TK_F64 && o.polish_K) ? TK_F64 : dt;
         int hp = 0;
-        int rc = run_hessian(Kh, dth, n, m, alpha + b * n, sb.hM, sb.hw, sb.hw_bytes, st, &hp);
+        int rc = run_hessian(Kh, dth, n, m, alpha + b * n, Jb, sb.hw, sb.hw_bytes, st, &hp);
         if (rc) return rc;
         hess_passes += hp;
-        Precond &P = pc[b];
-        P.J.resize((size_t)n * n);
-        TK_HIP_CHECK(hipMemcpyAsync(P.J.data(), sb.hM, (size_t)n * n * sizeof(double), hipMemcpyDeviceToHost, st));
-        TK_HIP_CHECK(hipStreamSynchronize(st));
-        P.have = true;
-        P.fresh = true;
         return TK_OK;
     };
-    // (J + lambda I)^{-1} of problem b to the device; J = 0 when none is held.
-    // A rounded J may miss positive definiteness by its rounding: shift more.
-    auto upload = [&](int64_t b) -> int {
-        const Precond &P = pc[b];
+    // (J_b + lambda I)^{-1} into the device preconditioner slot b, factored on
+    // the host (Cholesky); a rounded J may miss positive definiteness by its
+    // rounding: shift more.  J = 0 gives I / lambda directly.
+    auto refresh_inverse = [&](int64_t b, bool zero) -> int {
         std::vector<double> A((size_t)n * n, 0.0);
-        double tr = 0.0;
-        if (P.have) {
-            A = P.J;
+        if (zero) {
+            for (int64_t i = 0; i < n; ++i) A[i * n + i] = 1.0 / ps[b].lam;
+        } else {
+            TK_HIP_CHECK(hipMemcpyAsync(A.data(), sb.Jd + b * n * n, (size_t)n * n * sizeof(double),
+                                        hipMemcpyDeviceToHost, st));
+            TK_HIP_CHECK(hipStreamSynchronize(st));
+            double tr = 0.0;
             for (int64_t i = 0; i < n; ++i) tr += std::fabs(A[i * n + i]);
-        }
-        double shift = ps[b].lam;
-        for (int attempt = 0; attempt < 40; ++attempt) {
-            std::vector<double> T = A;
-            for (int64_t i = 0; i < n; ++i) T[i * n + i] += shift;
-            if (spd_inverse(T, (int)n)) {
-                TK_HIP_CHECK(hipMemcpyAsync(sb.P + b * n * n, T.data(), (size_t)n * n * sizeof(double),
-                                            hipMemcpyHostToDevice, st));
-                TK_HIP_CHECK(hipStreamSynchronize(st));
-                pc_updates[b]++;
-                return TK_OK;
+            double shift = ps[b].lam;
+            bool ok = false;
+            for (int attempt = 0; attempt < 40 && !ok; ++attempt) {
+                std::vector<double> T = A;
+                for (int64_t i = 0; i < n; ++i) T[i * n + i] += shift;
+                if (spd_inverse(T, (int)n)) {
+                    A.swap(T);
+                    ok = true;
+                } else {
+                    shift = ps[b].lam + (attempt == 0 ? 1e-7 : shift * 10.0) * (tr / (double)n + 1e-300);
+                }
             }
-            shift = ps[b].lam + (attempt == 0 ? 1e-7 : shift * 10.0) * (tr / (double)n + 1e-300);
+            if (!ok) return fail(TK_EHIP, "could not factor the preconditioner");
         }
-        return fail(TK_EHIP, "could not factor the preconditioner");
+        TK_HIP_CHECK(hipMemcpyAsync(sb.P + b * n * n, A.data(), (size_t)n * n * sizeof(double), hipMemcpyHostToDevice,
+                                    st));
+        TK_HIP_CHECK(hipStreamSynchronize(st));
+        pc_updates[b]++;
+        pc[b].dev = true;
+        pc[b].ident = zero;
+        return TK_OK;
+    };
+    // z = P r and r . z for every problem (P: the device preconditioner slots)
+    auto apply_pc = [&]() -> int {
+        TK_HIP_CHECK(vec_symv(sb.P, sb.r, sb.z, B, n, st));
+        TK_HIP_CHECK(vec_dot(sb.r, sb.z, n, sb.stats2, B, n, st));
+        return TK_OK;
     };
 
     const int phases = (dtype != TK_F64 && o.polish_K) ? 2 : 1;
@@ -725,6 +749,11 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
         // stops shrinking (the rounded tensor's noise floor)
         std::vector<double> best_gn(B, INFINITY);
         std::vector<int> stalled(B, 0);
+        // ... and keep its iterate of smallest gradient: at small lambda the
+        // rounded tensor's quartic form is not convex (its rounding reaches the
+        // null space of X^T), Newton steps can run off along it, and the polish
+        // then starts from the kept iterate
+        std::vector<double> kept_gn(B, INFINITY);
         for (int it = 0; it < max_newton; ++it) {
             bool any = false;
             for (int64_t b = 0; b < B; ++b) {
@@ -732,6 +761,15 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                 if (!std::isfinite(s.gn) || !std::isfinite(s.D)) {
                     s.done = true;
                     s.status = TK_ENAN;
+                }
+                if (!s.done && phases == 2 && phase == 0) {
+                    if (s.gn < kept_gn[b]) {
+                        kept_gn[b] = s.gn;
+                        TK_HIP_CHECK(hipMemcpyAsync(sb.best + b * n, alpha + b * n, n * sizeof(double),
+                                                    hipMemcpyDeviceToDevice, st));
+                    } else if (!(s.gn <= 1e3 * kept_gn[b])) {
+                        s.done = true;   // running off on the rounded tensor
+                    }
                 }
                 if (!s.done && o.fixed_iters <= 0 && s.gn <= tol * s.lam * s.an && s.an > 0) s.done = true;
                 if (!s.done && phases == 2 && phase == 0) {
@@ -745,23 +783,17 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                 any |= !s.done;
             }
             if (!any) break;
-            // ---- preconditioners: (re)assemble the Hessian where the last
-            // Newton step needed many CG steps or none is held yet
+            // ---- Hessians at the current iterates (the CG operator), and the
+            // inverse preconditioner where none is held or the last Newton
+            // step needed many CG steps
             if (use_pc) {
                 for (int64_t b = 0; b < B; ++b) {
                     if (ps[b].done) continue;
-                    Precond &P = pc[b];
-                    const bool zero_alpha = !(ps[b].an > 0);
-                    // at alpha = 0 the Hessian of an order m >= 4 dual is lambda I
-                    const bool need = zero_alpha ? (m == 2 && !P.have) : (!P.have || !P.fresh || ps[b].last_cg > refresh);
-                    if (need) {
-                        if ((rc = assemble(Kp, dt, b))) return rc;
-                        if ((rc = upload(b))) return rc;
-                        ps[b].pc_ready = true;
-                    } else if (!ps[b].pc_ready) {
-                        if ((rc = upload(b))) return rc;
-                        ps[b].pc_ready = true;
-                    }
+                    // at alpha = 0 the Hessian of an order m >= 4 dual term is zero
+                    const bool zero = !(ps[b].an > 0) && m >= 4;
+                    if ((rc = assemble(Kp, dt, b, zero))) return rc;
+                    if (!pc[b].dev || (pc[b].ident && !zero) || ps[b].last_cg > refresh)
+                        if ((rc = refresh_inverse(b, zero))) return rc;
                 }
             }
             // ---- preconditioned CG on (J + lam I) x = -grad for the active problems
@@ -773,7 +805,7 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
             std::vector<bool> cg_on(B);
             std::vector<int> cg_steps(B, 0);
             if (use_pc) {
-                TK_HIP_CHECK(vec_precond(sb.P, sb.r, sb.z, sb.stats2, B, n, st));        // z = P r
+                if ((rc = apply_pc())) return rc;                                       // z = P r
                 if ((rc = sync_copy(hz.data(), sb.stats2, B))) return rc;
             } else {
                 TK_HIP_CHECK(vec_lin2(sb.r, sb.r, one, zero, sb.z, B, n, st));            // z = r
@@ -791,9 +823,14 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                 bool anycg = false;
                 for (int64_t b = 0; b < B; ++b) anycg |= cg_on[b];
                 if (!anycg) break;
-                if ((rc = run_contract(Kp, dt, n, m, alpha, sb.dv, B, nullptr, sb.hd, hv_mode, sb.cw, sb.cw_bytes, st)))
-                    return rc;
-                passes++;
+                if (use_pc) {   // hd = J d
+                    TK_HIP_CHECK(vec_symv(sb.Jd, sb.dv, sb.hd, B, n, st));
+                } else {        // hd = (m-1) K . alpha^{m-2} d, one pass over the tensor
+                    if ((rc = run_contract(Kp, dt, n, m, alpha, sb.dv, B, nullptr, sb.hd, hv_mode, sb.cw,
+                                           sb.cw_bytes, st)))
+                        return rc;
+                    passes++;
+                }
                 TK_HIP_CHECK(vec_shift_dot(sb.dv, sb.hd, lam, sb.stats, B, n, st));
                 if ((rc = sync_copy(hd.data(), sb.stats, B))) return rc;
                 Coefs a{};
@@ -809,7 +846,7 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                 }
                 TK_HIP_CHECK(vec_cg_update(sb.x, sb.r, sb.dv, sb.hd, a, sb.stats, B, n, st));   // stats = r.r
                 if (use_pc) {
-                    TK_HIP_CHECK(vec_precond(sb.P, sb.r, sb.z, sb.stats2, B, n, st));          // z = P r, r.z
+                    if ((rc = apply_pc())) return rc;                                         // z = P r, r.z
                 } else {
                     TK_HIP_CHECK(vec_lin2(sb.r, sb.r, one, zero, sb.z, B, n, st));
                 }
@@ -833,7 +870,6 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
             for (int64_t b = 0; b < B; ++b)
                 if (!ps[b].done) {
                     ps[b].last_cg = cg_steps[b];
-                    if (cg_steps[b] > refresh) pc[b].fresh = false;
                 }
             // if CG produced nothing (zero curvature at the first step), fall back to steepest descent
             TK_HIP_CHECK(vec_dot(sb.x, sb.x, n, sb.stats, B, n, st));
@@ -913,7 +949,11 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
         for (int64_t b = 0; b < B; ++b) {
             ProblemState &s = ps[b];
             if (phases == 2 && phase == 0) {
-                if (s.status == TK_ENAN) {   // restart the polish from zero
+                if (std::isfinite(kept_gn[b])) {   // the polish starts from the kept iterate
+                    s.status = TK_OK;
+                    TK_HIP_CHECK(hipMemcpyAsync(alpha + b * n, sb.best + b * n, n * sizeof(double),
+                                                hipMemcpyDeviceToDevice, st));
+                } else if (s.status == TK_ENAN) {   // restart the polish from zero
                     s.status = TK_OK;
                     TK_HIP_CHECK(hipMemsetAsync(alpha + b * n, 0, n * sizeof(double), st));
                 }

@@ -272,6 +272,19 @@ inline size_t dtype_size(int dtype)
     return dtype == TK_F64 ? 8 : dtype == TK_F32 ? 4 : 2;
 }
 
+// Instrumentation of the passes that stream the packed tensor (tk_timing_*):
+// kinds 0 compensated contraction, 1 directional derivative, 2 plain
+// contraction, 3 and 4 the two streaming kernels of the Hessian.
+constexpr int kTimingKinds = 5;
+struct TimedLaunch {
+    hipEvent_t a, b;
+    int kind;
+    double bytes;
+    bool on;
+};
+TimedLaunch timing_begin(int kind, double bytes, hipStream_t st);
+void timing_end(TimedLaunch &t, hipStream_t st);
+
 inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
 }  // namespace tk

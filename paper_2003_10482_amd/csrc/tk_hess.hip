@@ -590,11 +590,16 @@ hipError_t launch_mp(const TIn *K, int64_t n, const double *alpha, double *J, co
                      const HessBuffers &b, hipStream_t st)
 {
     const int ni = h.nitems();
+    const double tensor_bytes = (double)packed_count(n, MP + 2) * (double)sizeof(TIn);
+    TimedLaunch tl = timing_begin(3, tensor_bytes, st);
     hess_tri_kernel<MP, TIn><<<(ni + 3) / 4, 256, 0, st>>>(K, alpha, (int)n, d.tiles, d.items, ni, d.tab, b.part);
+    timing_end(tl, st);
     hess_tri_reduce<<<dim3(kHessL / 256, h.ntiles()), 256, 0, st>>>(b.part, d.tiles, d.tile_items, (int)n, b.U);
     int S = 0;
     if constexpr (MP >= 2) {
+        tl = timing_begin(4, tensor_bytes, st);
         hess_unit_kernel<MP, TIn><<<h.rwaves(), 64, 0, st>>>(K, alpha, (int)n, d.rplan, d.tab, b.R, b.q);
+        timing_end(tl, st);
         hess_cross_kernel<MP><<<dim3(h.xs, (unsigned)n), 64, 0, st>>>(alpha, (int)n, b.R, b.q, d.tab, h.nq, h.xs,
                                                                       b.Y);
         S = h.xs;

@@ -148,28 +148,22 @@ inline unsigned grid_for(int64_t n)
     return (unsigned)(g < 1 ? 1 : g > 1024 ? 1024 : g);
 }
 
-// z_b = P_b r_b with P_b a symmetric n x n matrix ([B][n][n]; thread i reads
-// column i, so the loads are coalesced); out_b = r_b . z_b (compensated).
-// One workgroup per vector, n <= 256.
-__global__ void __launch_bounds__(256) precond_kernel(const double *__restrict__ P, const double *__restrict__ r,
-                                                      double *__restrict__ z, double *__restrict__ out, int n)
+// z_b = A_b x_b for symmetric row-major A_b [n][n]: one wave per output row,
+// lanes over the row, a shuffle reduction at the end.
+__global__ void __launch_bounds__(256) symv_kernel(const double *__restrict__ A, const double *__restrict__ x,
+                                                   double *__restrict__ z, int n)
 {
-    __shared__ DD sh[256];
-    __shared__ double rs[256];
-    const int b = blockIdx.x;
-    const int i = threadIdx.x;
-    if (i < n) rs[i] = r[(int64_t)b * n + i];
-    __syncthreads();
-    DD acc{0, 0};
-    if (i < n) {
-        const double *Pb = P + (int64_t)b * n * n;
-        double s = 0.0;
-        for (int j = 0; j < n; ++j) s = __builtin_fma(Pb[(int64_t)j * n + i], rs[j], s);
-        z[(int64_t)b * n + i] = s;
-        dd_fma(acc, s, rs[i]);
-    }
-    const DD t = block_sum_dd(acc, sh);
-    if (threadIdx.x == 0) out[b] = t.hi + t.lo;
+    const int b = blockIdx.y;
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= n) return;
+    const double *Ar = A + ((int64_t)b * n + row) * n;
+    const double *xb = x + (int64_t)b * n;
+    double s = 0.0;
+    for (int j = lane; j < n; j += 64) s = __builtin_fma(Ar[j], xb[j], s);
+#pragma unroll
+    for (int sh = 32; sh >= 1; sh >>= 1) s += __shfl_xor(s, sh);
+    if (lane == 0) z[(int64_t)b * n + row] = s;
 }
 
 }  // namespace
@@ -221,13 +215,10 @@ hipError_t vec_nonfinite(const double *x, int64_t len, int *flag, hipStream_t st
     return hipGetLastError();
 }
 
-hipError_t vec_precond(const double *P, const double *r, double *z, double *out, int64_t B, int64_t n,
-                       hipStream_t st)
+hipError_t vec_symv(const double *A, const double *x, double *z, int64_t B, int64_t n, hipStream_t st)
 {
-    if (n > 256) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(precond_kernel, dim3((unsigned)B), dim3(256), 0, st, P, r, z, out, (int)n);
+    hipLaunchKernelGGL(symv_kernel, dim3((unsigned)((n + 3) / 4), (unsigned)B), dim3(256), 0, st, A, x, z, (int)n);
     return hipGetLastError();
 }
-
 
 }  // namespace tk

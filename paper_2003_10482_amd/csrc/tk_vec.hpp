@@ -25,8 +25,7 @@ hipError_t vec_pow_mul(const double *u, const double *s, int p, double *out, int
                        hipStream_t st);
 hipError_t vec_sub(const double *a, const double *b, double *out, int64_t len, hipStream_t st);
 hipError_t vec_nonfinite(const double *x, int64_t len, int *flag, hipStream_t st);
-// z_b = P_b r_b (P_b symmetric [n][n], n <= 256) and out_b = r_b . z_b
-hipError_t vec_precond(const double *P, const double *r, double *z, double *out, int64_t B, int64_t n,
-                       hipStream_t st);
+// z_b = A_b x_b (A_b symmetric [n][n], row-major)
+hipError_t vec_symv(const double *A, const double *x, double *z, int64_t B, int64_t n, hipStream_t st);
 
 }  // namespace tk
