@@ -600,6 +600,36 @@ bool spd_inverse(std::vector<double> &A, int n)
     return true;
 }
 
+// Step length along a Newton direction p for an order-4 (or 2) dual: with
+// s1 = grad . p < 0, s2 = p . (J + lambda I) p, f3 = K . alpha p^3 and
+// f4 = K . p^4, D(alpha + t p) - D(alpha) = s1 t + s2 t^2/2 + f3 t^3 + f4 t^4/4
+// exactly.  Returns the first t > 0 where the derivative turns non-negative
+// (the minimiser when D is convex along p), bracketed on a logarithmic grid
+// and refined by bisection, at most tmax; 1 when p is not a descent direction.
+double quartic_step(double s1, double s2, double f3, double f4)
+{
+    constexpr double tmax = 8.0;
+    if (!(s1 < 0) || !std::isfinite(s1) || !std::isfinite(s2) || !std::isfinite(f3) || !std::isfinite(f4))
+        return 1.0;
+    auto dpsi = [&](double t) { return s1 + t * (s2 + t * (3.0 * f3 + t * f4)); };
+    double lo = 0.0, hi = -1.0;
+    for (int i = 0; i <= 320; ++i) {
+        const double t = std::min(tmax, std::pow(10.0, -14.0 + 0.05 * i));
+        if (dpsi(t) >= 0) {
+            hi = t;
+            break;
+        }
+        lo = t;
+        if (t == tmax) break;
+    }
+    if (hi < 0) return tmax;
+    for (int i = 0; i < 200 && hi - lo > 1e-15 * hi; ++i) {
+        const double mid = 0.5 * (lo + hi);
+        (dpsi(mid) >= 0 ? hi : lo) = mid;
+    }
+    return hi;
+}
+
 // Device slot b of the preconditioner holds an inverse (J' + lambda' I)^{-1}
 // from an earlier iterate (and, along a lambda path, an earlier lambda): a
 // stale inverse still preconditions the current system well.
@@ -889,6 +919,27 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
             TK_HIP_CHECK(vec_dot(sb.grad, sb.x, n, sb.stats, B, n, st));
             std::vector<double> slope(B), t(B, 1.0);
             if ((rc = sync_copy(slope.data(), sb.stats, B))) return rc;
+            if (use_pc && (m == 2 || m == 4)) {
+                // exact model of D along x: s2 from the assembled Hessian, and
+                // for m = 4 the cubic and quartic terms from one plain pass
+                // gt = K . x^3 (D is a quartic polynomial in the step length)
+                std::vector<double> s2(B), f3(B, 0.0), f4(B, 0.0);
+                TK_HIP_CHECK(vec_symv(sb.Jd, sb.x, sb.hd, B, n, st));
+                TK_HIP_CHECK(vec_shift_dot(sb.x, sb.hd, lam, sb.stats, B, n, st));
+                if ((rc = sync_copy(s2.data(), sb.stats, B))) return rc;
+                if (m == 4) {
+                    const int pm = dt == TK_F64 ? ACC_PLAIN64 : ACC_PLAIN32;
+                    if ((rc = run_contract(Kp, dt, n, m, sb.x, nullptr, B, sb.gt, nullptr, pm, sb.cw, sb.cw_bytes, st)))
+                        return rc;
+                    passes++;
+                    TK_HIP_CHECK(vec_dot(alpha, sb.gt, n, sb.stats, B, n, st));
+                    if ((rc = sync_copy(f3.data(), sb.stats, B))) return rc;
+                    TK_HIP_CHECK(vec_dot(sb.x, sb.gt, n, sb.stats, B, n, st));
+                    if ((rc = sync_copy(f4.data(), sb.stats, B))) return rc;
+                }
+                for (int64_t b = 0; b < B; ++b)
+                    if (!ps[b].done) t[b] = quartic_step(slope[b], s2[b], f3[b], f4[b]);
+            }
             std::vector<bool> ls(B);
             for (int64_t b = 0; b < B; ++b) ls[b] = !ps[b].done;
             for (int trial = 0; trial < 60; ++trial) {
