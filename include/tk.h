@@ -84,7 +84,10 @@ int tk_packed_bytes(int64_t n, int m, int dtype, int64_t *h_bytes);
  * K_t = k(x_{t_0}, .., x_{t_{m-1}}) for every sorted tuple t, stored in the
  * nested-loop order of Section 5).  The kernel value is computed in FP64 and
  * rounded to `dtype` (round-to-nearest-even) when stored into d_K, which must
- * hold tk_packed_bytes(n, m, dtype) bytes.
+ * hold tk_packed_bytes(n, m, dtype) bytes.  BF16 with an odd number of
+ * entries: the 2 bytes after the last entry are read together with it and
+ * this call sets them to zero (a BF16 array filled by other means must hold a
+ * finite value there).
  * Errors: TK_EINVAL (m < 2 or odd, n/d < 1, kernel/kparam invalid),
  * TK_EOVERFLOW, TK_EUNSUPPORTED (n > tk_max_points()), TK_EHIP.
  */

@@ -87,7 +87,9 @@ def empty_packed(n: int, m: int, dtype, device) -> torch.Tensor:
     count = packed_count(n, m)
     esz = {F64: 8, F32: 4, BF16: 2}[dt]
     total = (packed_bytes(n, m, dt) + esz - 1) // esz
-    return torch.empty(total, dtype=_TORCH_STORAGE[dt], device=device)[:count]
+    buf = torch.empty(total, dtype=_TORCH_STORAGE[dt], device=device)
+    buf[count:].zero_()   # padding read together with the last entries
+    return buf[:count]
 
 
 def contract_workspace(n: int, m: int, B: int, dtype) -> int:

@@ -677,10 +677,26 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
         TK_HIP_CHECK(hipStreamSynchronize(st));
         return TK_OK;
     };
+    // On FP64 storage, from a cold start (alpha = 0), the gradient passes use
+    // plain FP64 accumulation while ||grad|| is far above their rounding
+    // error, and compensated accumulation
+    // from the first of: ||grad|| <= 1e-5 ||y||, two Newton steps in a row
+    // that do not cut ||grad|| by 10 % (the error of a plain pass grows like
+    // |K| |alpha|^{m-1}, which at small lambda reaches ||grad||), a line search
+    // at its rounding floor.  Convergence is only decided on a compensated
+    // gradient.
+    bool accurate = true;
+    double ynorm = 0.0;
+    {
+        TK_HIP_CHECK(vec_dot(y, y, 0, sb.stats, 1, n, st));
+        TK_HIP_CHECK(hipMemcpyAsync(&ynorm, sb.stats, sizeof(double), hipMemcpyDeviceToHost, st));
+        TK_HIP_CHECK(hipStreamSynchronize(st));
+        ynorm = std::sqrt(ynorm);
+    }
     // gradient pass at `a` into (gdst, graddst), statistics to the host
     auto gradient = [&](const void *Kp, int dt, const double *a, double *gdst, double *graddst,
                         std::vector<double> &out) -> int {
-        int mode = dt == TK_F64 ? ACC_DD : ACC_PLAIN32;
+        int mode = dt == TK_F64 ? (accurate ? ACC_DD : ACC_PLAIN64) : ACC_PLAIN32;
         int rc = run_contract(Kp, dt, n, m, a, nullptr, B, gdst, nullptr, mode, sb.cw, sb.cw_bytes, st);
         if (rc) return rc;
         passes++;
@@ -762,15 +778,24 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
             ps[b].done = false;
             ps[b].status = TK_OK;
         }
+        accurate = true;   // plain passes only from a cold start (a warm start sits near the optimum)
+        auto take_stats = [&]() {
+            for (int64_t b = 0; b < B; ++b) {
+                ProblemState &s = ps[b];
+                s.ag = hst[4 * b];
+                s.aa = hst[4 * b + 1];
+                s.ya = hst[4 * b + 2];
+                s.gn = std::sqrt(hst[4 * b + 3]);
+                s.an = std::sqrt(s.aa);
+                s.D = inv_m * s.ag + 0.5 * s.lam * s.aa - s.ya;
+            }
+        };
         if ((rc = gradient(Kp, dt, alpha, sb.g, sb.grad, hst))) return rc;
-        for (int64_t b = 0; b < B; ++b) {
-            ProblemState &s = ps[b];
-            s.ag = hst[4 * b];
-            s.aa = hst[4 * b + 1];
-            s.ya = hst[4 * b + 2];
-            s.gn = std::sqrt(hst[4 * b + 3]);
-            s.an = std::sqrt(s.aa);
-            s.D = inv_m * s.ag + 0.5 * s.lam * s.aa - s.ya;
+        take_stats();
+        if (dt == TK_F64) {
+            bool cold = true;
+            for (int64_t b = 0; b < B; ++b) cold = cold && !(ps[b].an > 0);
+            accurate = !cold;
         }
         const int max_newton = o.fixed_iters > 0 ? o.fixed_iters : (o.max_newton > 0 ? o.max_newton : 100);
         double gn0[kMaxCoefs];
@@ -784,7 +809,25 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
         // null space of X^T), Newton steps can run off along it, and the polish
         // then starts from the kept iterate
         std::vector<double> kept_gn(B, INFINITY);
+        // accepted step length of the last Newton step (1 in the quadratic regime)
+        std::vector<double> last_t(B, 0.0);
+        std::vector<double> prev_gn(B, INFINITY);
+        std::vector<int> flat(B, 0);   // Newton steps in a row without a 10 % cut of ||grad||
         for (int it = 0; it < max_newton; ++it) {
+            if (!accurate) {   // near the optimum, stagnating, or a plain gradient claims convergence
+                bool sw = false;
+                for (int64_t b = 0; b < B; ++b) {
+                    if (ps[b].done || !std::isfinite(ps[b].gn)) continue;
+                    flat[b] = ps[b].gn > 0.9 * prev_gn[b] ? flat[b] + 1 : 0;
+                    prev_gn[b] = ps[b].gn;
+                    if (ps[b].gn <= 1e-5 * ynorm || ps[b].gn <= tol * ps[b].lam * ps[b].an || flat[b] >= 2) sw = true;
+                }
+                if (sw) {
+                    accurate = true;
+                    if ((rc = gradient(Kp, dt, alpha, sb.g, sb.grad, hst))) return rc;
+                    take_stats();
+                }
+            }
             bool any = false;
             for (int64_t b = 0; b < B; ++b) {
                 ProblemState &s = ps[b];
@@ -919,7 +962,10 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
             TK_HIP_CHECK(vec_dot(sb.grad, sb.x, n, sb.stats, B, n, st));
             std::vector<double> slope(B), t(B, 1.0);
             if ((rc = sync_copy(slope.data(), sb.stats, B))) return rc;
-            if (use_pc && (m == 2 || m == 4)) {
+            bool need_model = false;   // the model pass is skipped once every problem takes unit steps
+            for (int64_t b = 0; b < B; ++b)
+                if (!ps[b].done && !(std::fabs(last_t[b] - 1.0) <= 0.05)) need_model = true;
+            if (use_pc && (m == 2 || m == 4) && need_model) {
                 // exact model of D along x: s2 from the assembled Hessian, and
                 // for m = 4 the cubic and quartic terms from one plain pass
                 // gt = K . x^3 (D is a quartic polynomial in the step length)
@@ -942,6 +988,7 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
             }
             std::vector<bool> ls(B);
             for (int64_t b = 0; b < B; ++b) ls[b] = !ps[b].done;
+            bool floor_plain = false;
             for (int trial = 0; trial < 60; ++trial) {
                 bool anyls = false;
                 Coefs tc{};
@@ -976,11 +1023,15 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                         s.an = std::sqrt(s.aa);
                         s.D = Dn;
                         s.newton++;
+                        last_t[b] = t[b];
                     } else {
                         t[b] *= 0.5;
-                        if (t[b] < 1e-14) {   // no decrease possible: rounding floor
+                        if (t[b] < 1e-14) {   // no decrease visible: rounding floor of D
                             ls[b] = false;
-                            ps[b].done = true;
+                            if (accurate)
+                                ps[b].done = true;
+                            else
+                                floor_plain = true;   // ... of the plain passes: go on compensated
                         }
                     }
                 }
@@ -991,11 +1042,21 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                     TK_HIP_CHECK(vec_lin2(sb.grad, sb.hd, keep_c, acc_c, sb.grad, B, n, st));
                 }
             }
+            if (floor_plain) {
+                accurate = true;
+                if ((rc = gradient(Kp, dt, alpha, sb.g, sb.grad, hst))) return rc;
+                take_stats();
+            }
             if (o.verbose) {
                 for (int64_t b = 0; b < B; ++b)
                     fprintf(stderr, "[tk_solve] phase %d it %d lam %.3e |grad| %.3e D %.15e |a| %.3e cg %d\n", phase, it,
                             ps[b].lam, ps[b].gn, ps[b].D, ps[b].an, ps[b].cg);
             }
+        }
+        if (!accurate) {   // Newton limit reached on plain gradients: report a compensated one
+            accurate = true;
+            if ((rc = gradient(Kp, dt, alpha, sb.g, sb.grad, hst))) return rc;
+            take_stats();
         }
         for (int64_t b = 0; b < B; ++b) {
             ProblemState &s = ps[b];

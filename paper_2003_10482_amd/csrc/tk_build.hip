@@ -36,6 +36,13 @@ __device__ __forceinline__ void store_entry<uint16_t>(void *K, int64_t i, double
     reinterpret_cast<uint16_t *>(K)[i] = double_to_bf16(v);
 }
 
+// BF16 buffers are read a dword at a time: with an odd number of entries the
+// 2 bytes after the last one are read with it and must hold a finite value.
+__global__ void zero_bf16_tail(uint16_t *K, int64_t count)
+{
+    if (threadIdx.x == 0) K[count] = 0;
+}
+
 template <int M, typename TOut>
 __global__ void __launch_bounds__(256) build_kernel(const double *__restrict__ X, int n, int d,
                                                     int kernel, double kparam, int64_t rows,
@@ -144,6 +151,8 @@ hipError_t launch_build_m(const double *X, int n, int d, int kernel, double kpar
         hipLaunchKernelGGL((build_kernel<M, float>), grid, dim3(256), 0, st, X, n, d, kernel, kparam, rows, K);
     else
         hipLaunchKernelGGL((build_kernel<M, uint16_t>), grid, dim3(256), 0, st, X, n, d, kernel, kparam, rows, K);
+    if (dtype == TK_BF16 && (packed_count(n, M) & 1))   // the half dword after the last entry is read with it
+        hipLaunchKernelGGL(zero_bf16_tail, dim3(1), dim3(64), 0, st, static_cast<uint16_t *>(K), packed_count(n, M));
     return hipGetLastError();
 }
 

@@ -368,8 +368,6 @@ struct Pass {
         const int lim = blk_end < k_hi ? blk_end : k_hi;
         const int nrows = (lim - k) < RB ? (lim - k) : RB;
         const int lane_lo = k - KB * kWave;   // lanes >= lane_lo + r are on or right of the diagonal of row r
-        const bool tail = (n & (kWave - 1)) != 0;
-        const bool lane_in_n = (NB - 1) * kWave + lane < n;
 
         // ---- phase 1: loads of the batch (row r at offset off + r(n-k) - r(r-1)/2)
         VIn val[RB][SEG];
@@ -386,7 +384,7 @@ struct Pass {
                 if constexpr (ATAN) vald[r][j] = zero_like(VIn());
                 bool ok = r < nrows;
                 if (j == 0) ok = ok && (lane >= lane_lo + r);
-                if (b == NB - 1 && tail) ok = ok && lane_in_n;
+                ok = ok && b * kWave + lane < n;   // columns past n (any block: NB may exceed the blocks of n)
                 if (ok) {
                     val[r][j] = InL::load(rowp, b * kWave + lane);
                     if constexpr (ATAN) vald[r][j] = InL::load(rowd, b * kWave + lane);
@@ -513,26 +511,32 @@ struct Pass {
 
         // ---- phase 1: every lane loads every segment of every row through the
         // buffer descriptor.  Left of the diagonal the lane reads another row's
-        // entry (zeroed in phase 2); columns past n read finite entries or zeros
+        // entry (zeroed in phase 2); columns past n re-read column n-1
         // (their alpha and v are 0).
         VIn val[RB][SEG];
         VIn vald[RB][ATAN ? SEG : 1];
         constexpr uint32_t ES = (uint32_t)InL::kSize;
         // byte offset (from the descriptor base) of entry (row, column KB*64) of
         // row r; rows past the batch follow the same recurrence and read either
-        // real entries or zeros (their row coefficients are zero below).  In
-        // the last block, columns past n re-read column n-1 of the same row, so
-        // the last rows of the array stay inside it.
+        // real entries or zeros (their row coefficients are zero below).
+        // Columns past n re-read column n-1 of the same row, so the live rows
+        // never reach past the array (whose padding may hold anything).
         uint32_t so = (uint32_t)((off - k - e_base + KB * kWave) * (int64_t)ES);
         const uint32_t vlane = (uint32_t)lane * ES;
-        const int last_col = (NB - 1) * kWave + lane < n ? lane : n - 1 - (NB - 1) * kWave;
-        const uint32_t vtail = (uint32_t)(last_col - lane) * ES;   // 0 but for tail lanes
+        // lanes past column n-1 (in whichever block: NB may exceed the blocks
+        // that n fills) re-read column n-1 of the same row: 0 but for tail lanes
+        uint32_t vtail[SEG];
+#pragma unroll
+        for (int j = 0; j < SEG; ++j) {
+            const int l = (KB + j) * kWave + lane;
+            vtail[j] = l < n ? 0u : (uint32_t)(n - 1 - l) * ES;
+        }
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             const uint32_t vo = so + vlane;
 #pragma unroll
             for (int j = 0; j < SEG; ++j) {
-                const uint32_t o = vo + (uint32_t)(j * kWave) * ES + (KB + j == NB - 1 ? vtail : 0u);
+                const uint32_t o = vo + (uint32_t)(j * kWave) * ES + vtail[j];
                 val[r][j] = InL::load_buf(rs, o);
                 if constexpr (ATAN) vald[r][j] = InL::load_buf(rsd, o + (uint32_t)dshift);
             }

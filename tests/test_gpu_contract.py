@@ -254,3 +254,48 @@ def test_dense_shortcut_matches_closed_form():
     for b in range(3):
         ref = T.contract_closed(wl.X, A[b], 4)
         np.testing.assert_allclose(g[b], ref, rtol=1e-11, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("storage,acc,B", [("f32", tk.ACC_AUTO, 2), ("f32", tk.ACC_AUTO, 1), ("bf16", tk.ACC_AUTO, 2),
+                                           ("f64", tk.ACC_COMPENSATED, 1), ("f64", tk.ACC_F64, 2),
+                                           ("f64", tk.ACC_F32, 2)])
+@pytest.mark.parametrize("n,m", [(129, 4), (200, 4), (40, 6)])
+def test_workspace_contents_do_not_matter(n, m, storage, acc, B):
+    """Every workspace entry a pass reads is written first: a NaN-filled
+    workspace gives the same (finite) result as a zero-filled one."""
+    K = random_symmetric_packed_values(L.packed_count(n, m), seed=3 * n + m)
+    Kd, _ = _packed_dev(K, n, m, storage)
+    A = to_dev(random_alpha(n, seed=n + B, batch=B))
+    nbytes = tk.contract_workspace(n, m, B, Kd.dtype)
+    outs = []
+    for fill in (0.0, float("nan")):
+        work = torch.full(((nbytes + 7) // 8,), fill, dtype=torch.float64, device=device()).view(torch.uint8)
+        outs.append(to_np(tk.contract(Kd, A, acc=acc, work=work)))
+    assert np.all(np.isfinite(outs[1])), np.flatnonzero(~np.isfinite(outs[1]).all(axis=0))
+    np.testing.assert_array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("n,m", [(129, 4), (150, 4), (192, 4), (70, 4), (256, 2), (140, 2)])
+def test_memory_past_the_tensor_is_not_read(n, m, storage):
+    """NaN in the memory that follows the packed array (beyond the half dword
+    a BF16 array shares with its last entry) changes no result: columns past
+    n, in whichever column block they fall, never reach past the array
+    (n in (128, 192] runs the four-block kernels with a partial third block)."""
+    count = L.packed_count(n, m)
+    K = random_symmetric_packed_values(count, seed=7 * n + m)
+    dt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[storage]
+    code = {"f64": tk.F64, "f32": tk.F32, "bf16": tk.BF16}[storage]
+    vals = torch.as_tensor(K, device=device()).to(dt)
+    A = to_dev(random_alpha(n, seed=n, batch=2))
+    V = to_dev(random_alpha(n, seed=n + 1, batch=2))
+    res = []
+    for fill in (0.0, float("nan")):
+        buf = torch.full((count + 4096,), fill, dtype=dt, device=device())
+        buf[:count + (count & 1)] = 0
+        buf[:count] = vals
+        Kd = tk.PackedTensor(buf[:count], n, m, code)
+        res.append([to_np(tk.contract(Kd, A)), to_np(tk.hvp(Kd, A, V))])
+    for a, b in zip(res[0], res[1]):
+        assert np.all(np.isfinite(b))
+        np.testing.assert_array_equal(a, b)

@@ -91,3 +91,19 @@ def test_hessian_full_size_and_reproducible():
     Jabs = 3.0 * (aX * (aX.T @ np.abs(a)) ** 2) @ aX.T
     bound = (_chain(256, 4) + wl.X.shape[1]) * U64 * Jabs
     assert np.all(np.abs(J1 - Jr) <= bound)
+
+
+@pytest.mark.parametrize("n,m", [(129, 4), (13, 6), (70, 2)])
+def test_hessian_workspace_contents_do_not_matter(n, m):
+    import torch
+    from gpu_util import device
+    Kh = random_symmetric_packed_values(packed_count(n, m), seed=n)
+    a = to_dev(random_alpha(n, seed=1))
+    K, _ = _packed_dev(Kh, n, m)
+    nbytes = tk.hessian_workspace(n, m)
+    outs = []
+    for fill in (0.0, float("nan")):
+        work = torch.full(((nbytes + 7) // 8,), fill, dtype=torch.float64, device=device()).view(torch.uint8)
+        outs.append(to_np(tk.hessian(K, a, work=work)))
+    assert np.all(np.isfinite(outs[1]))
+    np.testing.assert_array_equal(outs[0], outs[1])
