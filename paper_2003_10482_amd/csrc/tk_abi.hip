@@ -555,6 +555,22 @@ SolveBuffers carve(void *work, int64_t n, int m, int64_t B, size_t total)
     return s;
 }
 
+// a . b over [k0, k1) with four independent partial sums (the host compiler
+// may not reassociate a single chain; four chains keep its FP units busy)
+double dot4(const double *a, const double *b, int k0, int k1)
+{
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int k = k0;
+    for (; k + 3 < k1; k += 4) {
+        s0 += a[k] * b[k];
+        s1 += a[k + 1] * b[k + 1];
+        s2 += a[k + 2] * b[k + 2];
+        s3 += a[k + 3] * b[k + 3];
+    }
+    for (; k < k1; ++k) s0 += a[k] * b[k];
+    return (s0 + s1) + (s2 + s3);
+}
+
 // Inverse of a symmetric positive definite matrix (row-major, n x n) through
 // its Cholesky factor A = L L^T: W = L^{-1} by forward substitution, then
 // A^{-1} = W^T W.  Returns false when a pivot is not positive.
@@ -563,16 +579,13 @@ bool spd_inverse(std::vector<double> &A, int n)
     std::vector<double> L((size_t)n * n, 0.0);
     for (int j = 0; j < n; ++j) {
         const double *Lj = &L[(size_t)j * n];
-        double d = A[(size_t)j * n + j];
-        for (int k = 0; k < j; ++k) d -= Lj[k] * Lj[k];
+        const double d = A[(size_t)j * n + j] - dot4(Lj, Lj, 0, j);
         if (!(d > 0) || !std::isfinite(d)) return false;
         const double ljj = std::sqrt(d);
         L[(size_t)j * n + j] = ljj;
         for (int i = j + 1; i < n; ++i) {
             const double *Li = &L[(size_t)i * n];
-            double t = A[(size_t)i * n + j];
-            for (int k = 0; k < j; ++k) t -= Li[k] * Lj[k];
-            L[(size_t)i * n + j] = t / ljj;
+            L[(size_t)i * n + j] = (A[(size_t)i * n + j] - dot4(Li, Lj, 0, j)) / ljj;
         }
     }
     // column c of W: W[c][c] = 1/L[c][c], W[i][c] = -(sum_{c<=k<i} L[i][k] W[k][c]) / L[i][i];
@@ -583,17 +596,13 @@ bool spd_inverse(std::vector<double> &A, int n)
         wc[c] = 1.0 / L[(size_t)c * n + c];
         for (int i = c + 1; i < n; ++i) {
             const double *Li = &L[(size_t)i * n];
-            double t = 0.0;
-            for (int k = c; k < i; ++k) t += Li[k] * wc[k];
-            wc[i] = -t / Li[i];
+            wc[i] = -dot4(Li, wc, c, i) / Li[i];
         }
     }
     // (W^T W)[r][c] = sum_{k >= max(r,c)} W[k][r] W[k][c] = Wt[r] . Wt[c] over k >= max(r, c)
     for (int r = 0; r < n; ++r)
         for (int c = 0; c <= r; ++c) {
-            const double *wr = &Wt[(size_t)r * n], *wc = &Wt[(size_t)c * n];
-            double t = 0.0;
-            for (int k = r; k < n; ++k) t += wr[k] * wc[k];
+            const double t = dot4(&Wt[(size_t)r * n], &Wt[(size_t)c * n], r, n);
             A[(size_t)r * n + c] = t;
             A[(size_t)c * n + r] = t;
         }
@@ -667,7 +676,7 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
     }
     int passes = 0, hess_passes = 0;
     std::vector<int> pc_updates(B, 0);
-    std::vector<double> hst(B * 4), hd(B), hr(B), hz(B);
+    std::vector<double> hst(B * 4), hd(B), hr(B);
     const double inv_m = 1.0 / m;
     const bool use_pc = o.precond != 0 && n <= 256;
     const int refresh = o.precond_refresh > 0 ? o.precond_refresh : 8;
@@ -679,12 +688,12 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
     };
     // On FP64 storage, from a cold start (alpha = 0), the gradient passes use
     // plain FP64 accumulation while ||grad|| is far above their rounding
-    // error, and compensated accumulation
-    // from the first of: ||grad|| <= 1e-5 ||y||, two Newton steps in a row
-    // that do not cut ||grad|| by 10 % (the error of a plain pass grows like
-    // |K| |alpha|^{m-1}, which at small lambda reaches ||grad||), a line search
-    // at its rounding floor.  Convergence is only decided on a compensated
-    // gradient.
+    // error, and compensated accumulation from the first of: ||grad|| <=
+    // 1e-5 ||y||; two Newton steps in a row that neither cut ||grad|| by 10 %
+    // nor decrease D by more than 1e-9 of it (the error of a plain pass grows
+    // like |K| |alpha|^{m-1}, which at small lambda reaches ||grad||); a line
+    // search at its rounding floor.  Convergence is only decided on a
+    // compensated gradient.
     bool accurate = true;
     double ynorm = 0.0;
     {
@@ -759,12 +768,6 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
         pc[b].ident = zero;
         return TK_OK;
     };
-    // z = P r and r . z for every problem (P: the device preconditioner slots)
-    auto apply_pc = [&]() -> int {
-        TK_HIP_CHECK(vec_symv(sb.P, sb.r, sb.z, B, n, st));
-        TK_HIP_CHECK(vec_dot(sb.r, sb.z, n, sb.stats2, B, n, st));
-        return TK_OK;
-    };
 
     const int phases = (dtype != TK_F64 && o.polish_K) ? 2 : 1;
     int rc = TK_OK;
@@ -811,15 +814,19 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
         std::vector<double> kept_gn(B, INFINITY);
         // accepted step length of the last Newton step (1 in the quadratic regime)
         std::vector<double> last_t(B, 0.0);
-        std::vector<double> prev_gn(B, INFINITY);
-        std::vector<int> flat(B, 0);   // Newton steps in a row without a 10 % cut of ||grad||
+        std::vector<double> prev_gn(B, INFINITY), prev_D(B, INFINITY);
+        std::vector<int> flat(B, 0);   // Newton steps in a row without progress (see below)
         for (int it = 0; it < max_newton; ++it) {
             if (!accurate) {   // near the optimum, stagnating, or a plain gradient claims convergence
                 bool sw = false;
                 for (int64_t b = 0; b < B; ++b) {
                     if (ps[b].done || !std::isfinite(ps[b].gn)) continue;
-                    flat[b] = ps[b].gn > 0.9 * prev_gn[b] ? flat[b] + 1 : 0;
+                    // no 10 % cut of ||grad|| and (next to) no decrease of D: the
+                    // plain passes' rounding, not the damped phase of Newton
+                    const bool no_gain = !(prev_D[b] - ps[b].D > 1e-9 * std::fabs(ps[b].D));
+                    flat[b] = (ps[b].gn > 0.9 * prev_gn[b] && no_gain) ? flat[b] + 1 : 0;
                     prev_gn[b] = ps[b].gn;
+                    prev_D[b] = ps[b].D;
                     if (ps[b].gn <= 1e-5 * ynorm || ps[b].gn <= tol * ps[b].lam * ps[b].an || flat[b] >= 2) sw = true;
                 }
                 if (sw) {
@@ -869,81 +876,75 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                         if ((rc = refresh_inverse(b, zero))) return rc;
                 }
             }
-            // ---- preconditioned CG on (J + lam I) x = -grad for the active problems
-            Coefs zc{}, act{};
+            // ---- CG on (J + lam I) x = -grad for the active problems, truncated at
+            // ||r|| <= eta ||grad|| (Eisenstat-Walker forcing)
+            Coefs act{};
             for (int64_t b = 0; b < B; ++b) act.c[b] = ps[b].done ? 0.0 : 1.0;
-            TK_HIP_CHECK(vec_lin2(sb.grad, sb.grad, zero, zero, sb.x, B, n, st));         // x = 0
-            TK_HIP_CHECK(vec_lin2(sb.grad, sb.grad, minus1, zero, sb.r, B, n, st));       // r = -grad
-            std::vector<double> rz(B), eta(B);
-            std::vector<bool> cg_on(B);
-            std::vector<int> cg_steps(B, 0);
-            if (use_pc) {
-                if ((rc = apply_pc())) return rc;                                       // z = P r
-                if ((rc = sync_copy(hz.data(), sb.stats2, B))) return rc;
-            } else {
-                TK_HIP_CHECK(vec_lin2(sb.r, sb.r, one, zero, sb.z, B, n, st));            // z = r
-                for (int64_t b = 0; b < B; ++b) hz[b] = ps[b].gn * ps[b].gn;
-            }
-            TK_HIP_CHECK(vec_lin2(sb.z, sb.z, one, zero, sb.dv, B, n, st));               // d = z
-            for (int64_t b = 0; b < B; ++b) {
-                rz[b] = hz[b];
-                const double f = std::sqrt(ps[b].gn / gn0[b]);
-                eta[b] = std::min(0.5, std::max(f, 1e-12));
-                cg_on[b] = !ps[b].done && ps[b].gn > 0 && rz[b] > 0;
-            }
             const int max_cg = o.max_cg > 0 ? o.max_cg : 2000;
-            for (int j = 0; j < max_cg; ++j) {
-                bool anycg = false;
-                for (int64_t b = 0; b < B; ++b) anycg |= cg_on[b];
-                if (!anycg) break;
-                if (use_pc) {   // hd = J d
-                    TK_HIP_CHECK(vec_symv(sb.Jd, sb.dv, sb.hd, B, n, st));
-                } else {        // hd = (m-1) K . alpha^{m-2} d, one pass over the tensor
-                    if ((rc = run_contract(Kp, dt, n, m, alpha, sb.dv, B, nullptr, sb.hd, hv_mode, sb.cw,
-                                           sb.cw_bytes, st)))
+            std::vector<int> cg_steps(B, 0);
+            std::vector<double> eta(B);
+            for (int64_t b = 0; b < B; ++b) eta[b] = std::min(0.5, std::max(std::sqrt(ps[b].gn / gn0[b]), 1e-12));
+            if (use_pc) {
+                // on the dense system, preconditioned, entirely on the device:
+                // one launch and one synchronisation per Newton step
+                Coefs etac{};
+                for (int64_t b = 0; b < B; ++b) etac.c[b] = eta[b];
+                int *dsteps = reinterpret_cast<int *>(sb.stats2);
+                TK_HIP_CHECK(vec_cg_dense(sb.Jd, sb.P, sb.grad, lam, etac, act, B, n, max_cg, sb.x, dsteps, st));
+                TK_HIP_CHECK(hipMemcpyAsync(cg_steps.data(), dsteps, B * sizeof(int), hipMemcpyDeviceToHost, st));
+                TK_HIP_CHECK(hipStreamSynchronize(st));
+                for (int64_t b = 0; b < B; ++b)
+                    if (!ps[b].done) ps[b].cg += cg_steps[b];
+            } else {
+                // unpreconditioned, every product one directional-derivative pass over the tensor
+                std::vector<double> rz(B);
+                std::vector<bool> cg_on(B);
+                TK_HIP_CHECK(vec_lin2(sb.grad, sb.grad, zero, zero, sb.x, B, n, st));     // x = 0
+                TK_HIP_CHECK(vec_lin2(sb.grad, sb.grad, minus1, zero, sb.r, B, n, st));   // r = -grad
+                TK_HIP_CHECK(vec_lin2(sb.r, sb.r, one, zero, sb.dv, B, n, st));           // d = r
+                for (int64_t b = 0; b < B; ++b) {
+                    rz[b] = ps[b].gn * ps[b].gn;
+                    cg_on[b] = !ps[b].done && ps[b].gn > 0;
+                }
+                for (int j = 0; j < max_cg; ++j) {
+                    bool anycg = false;
+                    for (int64_t b = 0; b < B; ++b) anycg |= cg_on[b];
+                    if (!anycg) break;
+                    if ((rc = run_contract(Kp, dt, n, m, alpha, sb.dv, B, nullptr, sb.hd, hv_mode, sb.cw, sb.cw_bytes,
+                                           st)))
                         return rc;
                     passes++;
-                }
-                TK_HIP_CHECK(vec_shift_dot(sb.dv, sb.hd, lam, sb.stats, B, n, st));
-                if ((rc = sync_copy(hd.data(), sb.stats, B))) return rc;
-                Coefs a{};
-                for (int64_t b = 0; b < B; ++b) {
-                    if (!cg_on[b]) continue;
-                    if (!(hd[b] > 0) || !std::isfinite(hd[b])) {   // no positive curvature along d
-                        cg_on[b] = false;
-                        continue;
+                    TK_HIP_CHECK(vec_shift_dot(sb.dv, sb.hd, lam, sb.stats, B, n, st));
+                    if ((rc = sync_copy(hd.data(), sb.stats, B))) return rc;
+                    Coefs a{};
+                    for (int64_t b = 0; b < B; ++b) {
+                        if (!cg_on[b]) continue;
+                        if (!(hd[b] > 0) || !std::isfinite(hd[b])) {   // no positive curvature along d
+                            cg_on[b] = false;
+                            continue;
+                        }
+                        a.c[b] = rz[b] / hd[b];
+                        ps[b].cg++;
+                        cg_steps[b]++;
                     }
-                    a.c[b] = rz[b] / hd[b];
-                    ps[b].cg++;
-                    cg_steps[b]++;
-                }
-                TK_HIP_CHECK(vec_cg_update(sb.x, sb.r, sb.dv, sb.hd, a, sb.stats, B, n, st));   // stats = r.r
-                if (use_pc) {
-                    if ((rc = apply_pc())) return rc;                                         // z = P r, r.z
-                } else {
-                    TK_HIP_CHECK(vec_lin2(sb.r, sb.r, one, zero, sb.z, B, n, st));
-                }
-                if ((rc = sync_copy(hr.data(), sb.stats, B))) return rc;
-                if (use_pc && (rc = sync_copy(hz.data(), sb.stats2, B))) return rc;
-                Coefs beta{}, keep{};
-                for (int64_t b = 0; b < B; ++b) {
-                    keep.c[b] = 1.0;
-                    if (!cg_on[b]) continue;
-                    if (std::sqrt(hr[b]) <= eta[b] * ps[b].gn) {
-                        cg_on[b] = false;
-                        continue;
+                    TK_HIP_CHECK(vec_cg_update(sb.x, sb.r, sb.dv, sb.hd, a, sb.stats, B, n, st));   // stats = r.r
+                    if ((rc = sync_copy(hr.data(), sb.stats, B))) return rc;
+                    Coefs beta{}, keep{};
+                    for (int64_t b = 0; b < B; ++b) {
+                        keep.c[b] = 1.0;
+                        if (!cg_on[b]) continue;
+                        if (std::sqrt(hr[b]) <= eta[b] * ps[b].gn) {
+                            cg_on[b] = false;
+                            continue;
+                        }
+                        beta.c[b] = hr[b] / rz[b];
+                        rz[b] = hr[b];
                     }
-                    const double rzn = use_pc ? hz[b] : hr[b];
-                    beta.c[b] = rzn / rz[b];
-                    rz[b] = rzn;
+                    TK_HIP_CHECK(vec_lin2(sb.r, sb.dv, keep, beta, sb.dv, B, n, st));   // d = r + beta d
                 }
-                // d = z + beta d for the problems still iterating
-                TK_HIP_CHECK(vec_lin2(sb.z, sb.dv, keep, beta, sb.dv, B, n, st));
             }
             for (int64_t b = 0; b < B; ++b)
-                if (!ps[b].done) {
-                    ps[b].last_cg = cg_steps[b];
-                }
+                if (!ps[b].done) ps[b].last_cg = cg_steps[b];
             // if CG produced nothing (zero curvature at the first step), fall back to steepest descent
             TK_HIP_CHECK(vec_dot(sb.x, sb.x, n, sb.stats, B, n, st));
             if ((rc = sync_copy(hr.data(), sb.stats, B))) return rc;

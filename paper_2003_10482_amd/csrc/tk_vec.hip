@@ -166,6 +166,83 @@ __global__ void __launch_bounds__(256) symv_kernel(const double *__restrict__ A,
     if (lane == 0) z[(int64_t)b * n + row] = s;
 }
 
+// Sum over the 256 threads of a workgroup (4 waves): shuffles, then the four
+// wave sums through LDS; every thread returns the total.
+__device__ __forceinline__ double block_sum256(double v, double *sh4)
+{
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) v += __shfl_xor(v, s);
+    __syncthreads();   // sh4 free (previous readers done)
+    if ((threadIdx.x & 63) == 0) sh4[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return (sh4[0] + sh4[1]) + (sh4[2] + sh4[3]);
+}
+
+// Preconditioned CG on (J_b + lam_b I) x = -grad_b, one problem per
+// workgroup, thread i owning component i (n <= 256); J_b and P_b symmetric
+// [n][n] (P_b the preconditioner), read by columns so the loads of a step
+// are coalesced.  Stops at ||r|| <= eta_b ||grad_b||, at non-positive
+// curvature along the search direction, or after max_it steps; x_b = 0 and
+// steps_b = 0 for inactive problems (act_b = 0).
+__global__ void __launch_bounds__(256) cg_dense_kernel(const double *__restrict__ J, const double *__restrict__ P,
+                                                       const double *__restrict__ grad, Coefs lam, Coefs eta,
+                                                       Coefs act, int n, int max_it, double *__restrict__ x,
+                                                       int *__restrict__ steps)
+{
+    __shared__ double sv[256];   // the vector of the next product (d, then r)
+    __shared__ double sh4[4];
+    const int b = blockIdx.x;
+    const int i = threadIdx.x;
+    const bool in = i < n;
+    const double *Jb = J + (int64_t)b * n * n;
+    const double *Pb = P + (int64_t)b * n * n;
+    double *xb = x + (int64_t)b * n;
+    if (!(act.c[b] > 0)) {
+        if (in) xb[i] = 0.0;
+        if (i == 0) steps[b] = 0;
+        return;
+    }
+    const double lb = lam.c[b];
+    auto matvec = [&](const double *M, double v) -> double {   // (M v)_i, v_i given per thread
+        __syncthreads();   // sv free
+        sv[i] = in ? v : 0.0;
+        __syncthreads();
+        double s = 0.0;
+        if (in)
+            for (int j = 0; j < n; ++j) s = __builtin_fma(M[(int64_t)j * n + i], sv[j], s);
+        return s;
+    };
+    const double gi = in ? grad[(int64_t)b * n + i] : 0.0;
+    const double gn = sqrt(block_sum256(gi * gi, sh4));
+    double xi = 0.0, ri = -gi;
+    double zi = matvec(Pb, ri);
+    double rz = block_sum256(ri * zi, sh4);
+    double di = zi;
+    int it = 0;
+    if (gn > 0 && rz > 0) {
+        for (; it < max_it; ++it) {
+            const double hi = matvec(Jb, di) + lb * di;
+            const double dhd = block_sum256(di * hi, sh4);
+            if (!(dhd > 0) || !isfinite(dhd)) break;   // no positive curvature along d
+            const double a = rz / dhd;
+            xi = __builtin_fma(a, di, xi);
+            ri = __builtin_fma(-a, hi, ri);
+            const double rr = block_sum256(ri * ri, sh4);
+            if (sqrt(rr) <= eta.c[b] * gn) {
+                ++it;
+                break;
+            }
+            zi = matvec(Pb, ri);
+            const double rzn = block_sum256(ri * zi, sh4);
+            const double beta = rzn / rz;
+            rz = rzn;
+            di = __builtin_fma(beta, di, zi);
+        }
+    }
+    if (in) xb[i] = xi;
+    if (i == 0) steps[b] = it;
+}
+
 }  // namespace
 
 hipError_t vec_grad(const double *g, const double *alpha, const double *y, const Coefs &lam,
@@ -218,6 +295,15 @@ hipError_t vec_nonfinite(const double *x, int64_t len, int *flag, hipStream_t st
 hipError_t vec_symv(const double *A, const double *x, double *z, int64_t B, int64_t n, hipStream_t st)
 {
     hipLaunchKernelGGL(symv_kernel, dim3((unsigned)((n + 3) / 4), (unsigned)B), dim3(256), 0, st, A, x, z, (int)n);
+    return hipGetLastError();
+}
+
+hipError_t vec_cg_dense(const double *J, const double *P, const double *grad, const Coefs &lam, const Coefs &eta,
+                        const Coefs &act, int64_t B, int64_t n, int max_it, double *x, int *steps, hipStream_t st)
+{
+    if (n > 256) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(cg_dense_kernel, dim3((unsigned)B), dim3(256), 0, st, J, P, grad, lam, eta, act, (int)n, max_it,
+                       x, steps);
     return hipGetLastError();
 }
 

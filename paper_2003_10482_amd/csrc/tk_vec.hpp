@@ -25,6 +25,10 @@ hipError_t vec_pow_mul(const double *u, const double *s, int p, double *out, int
                        hipStream_t st);
 hipError_t vec_sub(const double *a, const double *b, double *out, int64_t len, hipStream_t st);
 hipError_t vec_nonfinite(const double *x, int64_t len, int *flag, hipStream_t st);
+// Preconditioned CG on (J_b + lam_b I) x_b = -grad_b on the device (one
+// workgroup per problem, n <= 256); steps[b] receives the CG steps taken.
+hipError_t vec_cg_dense(const double *J, const double *P, const double *grad, const Coefs &lam, const Coefs &eta,
+                        const Coefs &act, int64_t B, int64_t n, int max_it, double *x, int *steps, hipStream_t st);
 // z_b = A_b x_b (A_b symmetric [n][n], row-major)
 hipError_t vec_symv(const double *A, const double *x, double *z, int64_t B, int64_t n, hipStream_t st);
 
