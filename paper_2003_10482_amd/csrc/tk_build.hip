@@ -5,8 +5,9 @@
 // linear kernel K[P, l] = sum_j q_P[j] x_l[j] with q_P = prod_{i in P} x_i
 // (elementwise), i.e. a product of the (rows x d) matrix Q with X^T restricted
 // to l >= P_last.  A workgroup computes a 64-row x 64-column tile: Q and X
-// chunks are staged in LDS and every thread accumulates a 4 x 4 register tile
-// in FP64 (VALU).  The kernel value (linear / polynomial / exponential) is
+// chunks are staged in LDS and each wave accumulates a 32 x 32 quarter with
+// FP64 MFMA (v_mfma_f64_16x16x4f64, 2 x 2 tiles: every operand read from LDS
+// feeds 16 FMAs).  The kernel value (linear / polynomial / exponential) is
 // formed in FP64 and rounded once to the storage type.
 #include "tk_common.hpp"
 
@@ -16,7 +17,7 @@ namespace {
 
 constexpr int TR = 64;    // rows per tile
 constexpr int TC = 64;    // columns per tile
-constexpr int FCH = 16;   // features per LDS chunk
+constexpr int FCH = 32;   // features per LDS chunk (8 MFMA k-steps of 4)
 
 template <typename TOut>
 __device__ __forceinline__ void store_entry(void *K, int64_t i, double v);
@@ -42,6 +43,8 @@ __global__ void zero_bf16_tail(uint16_t *K, int64_t count)
 {
     if (threadIdx.x == 0) K[count] = 0;
 }
+
+typedef double v4d __attribute__((ext_vector_type(4)));
 
 template <int M, typename TOut>
 __global__ void __launch_bounds__(256) build_kernel(const double *__restrict__ X, int n, int d,
@@ -81,12 +84,19 @@ __global__ void __launch_bounds__(256) build_kernel(const double *__restrict__ X
     __syncthreads();
     if (kmin > c0 + TC - 1 || c0 >= n) return;   // every row starts right of this tile
 
-    const int tr = t / 16, tc = t % 16;   // 4x4 micro-tile
-    double acc[4][4];
+    // wave w owns the 32 x 32 quarter (rows 32 (w / 2), columns 32 (w % 2))
+    // as 2 x 2 MFMA tiles of 16 x 16; v_mfma_f64_16x16x4f64 takes
+    //   A: lane holds A[row0 + lane%16][k0 + lane/16]
+    //   B: lane holds B[k0 + lane/16][col0 + lane%16]
+    //   C: lane holds C[row0 + 4e + lane/16][col0 + lane%16], e = 0..3
+    const int lane = t & 63, w = t >> 6;
+    const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
+    const int li = lane & 15, lk = lane >> 4;
+    v4d acc[2][2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+        for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
     for (int f0 = 0; f0 < d; f0 += FCH) {
         // stage q_P[f] for the tile rows and x_l[f] for the tile columns
@@ -103,40 +113,43 @@ __global__ void __launch_bounds__(256) build_kernel(const double *__restrict__ X
         }
         __syncthreads();
 #pragma unroll
-        for (int f = 0; f < FCH; ++f) {
-            double qa[4], xb[4];
+        for (int s = 0; s < FCH / 4; ++s) {
+            const int f = 4 * s + lk;
+            double a[2], b[2];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) qa[i] = qs[f][tr * 4 + i];
+            for (int i = 0; i < 2; ++i) a[i] = qs[f][wr + 16 * i + li];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) xb[j] = xs[f][tc * 4 + j];
+            for (int j = 0; j < 2; ++j) b[j] = xs[f][wc + 16 * j + li];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_fma(qa[i], xb[j], acc[i][j]);
+                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int r = tr * 4 + i;
-        const int k = rk[r];
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int l = c0 + tc * 4 + j;
-            if (l >= k && l < n) {
-                double v = acc[i][j];
-                if (kernel == TK_POLY) {
-                    const int s = (int)kparam;
-                    double pw = 1.0;
-                    for (int e = 0; e < s; ++e) pw *= v;
-                    v = pw;
-                } else if (kernel == TK_EXP) {
-                    v = exp(v);
+        for (int e = 0; e < 4; ++e) {
+            const int r = wr + 16 * i + 4 * e + lk;
+            const int k = rk[r];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int l = c0 + wc + 16 * j + li;
+                if (l >= k && l < n) {
+                    double v = acc[i][j][e];
+                    if (kernel == TK_POLY) {
+                        const int sdeg = (int)kparam;
+                        double pw = 1.0;
+                        for (int q = 0; q < sdeg; ++q) pw *= v;
+                        v = pw;
+                    } else if (kernel == TK_EXP) {
+                        v = exp(v);
+                    }
+                    store_entry<TOut>(K, roff[r] + (l - k), v);
                 }
-                store_entry<TOut>(K, roff[r] + (l - k), v);
             }
         }
-    }
 }
 
 template <int M>
