@@ -8,7 +8,9 @@ solve the dual to ||grad D|| <= 1e-11 lambda ||alpha|| with the Newton solver
 Hessian assembled in two passes at every Newton step, CG on the dense
 system), recover w = (X^T alpha)^3, take the 2-std support and predict on X.
 After the timed steps, the 64-value lambda path of the same data is solved
-and timed separately ("lambda_path").
+and timed separately ("lambda_path"): by continuation, as 64 independent
+cold solves (the batched form's speedup at equal support accuracy), and
+with FP32/BF16 storage finished on the FP64 tensor.
 
 value = passes over the packed tensor per second across the timed steps
         (contractions, and the two streaming passes of each Hessian).
@@ -137,25 +139,49 @@ def lambda_path(tk, torch, dev) -> dict:
     K = tk.build_packed_tensor(X, wl.m, dtype="f64")
     out = {"lambdas": len(wl.lambdas), "range": [float(wl.lambdas.min()), float(wl.lambdas.max())]}
     true = set(wl.support.tolist())
-    for tol in (1e-10, 1e-4):
-        tk.solve_dual(K, y, wl.lambdas[-2:], tol=tol)   # warm the plan caches
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        alpha, infos = tk.solve_dual(K, y, wl.lambdas, tol=tol)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+
+    def f1_of(alpha):
         W = tk.primal_weights(X, alpha, wl.m)
         mask, _ = tk.support(W)
         m = mask.cpu().numpy().astype(bool)
         f1 = []
-        for b in range(len(wl.lambdas)):
+        for b in range(m.shape[0]):
             sel = set(np.flatnonzero(m[b]).tolist())
             tp = len(sel & true)
             f1.append(0.0 if tp == 0 else 2 * tp / (len(sel) + len(true)))
-        out[f"tol_{tol:g}"] = {"seconds": dt, "passes": sum(i["passes"] + i["hess_passes"] for i in infos),
-                               "newton_iters": sum(i["newton_iters"] for i in infos),
-                               "all_converged": all(i["status"] == 0 for i in infos),
-                               "support_f1_min": min(f1), "support_f1_mean": float(np.mean(f1))}
+        return f1
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = fn()
+        torch.cuda.synchronize()
+        return res, time.perf_counter() - t0
+
+    for tol in (1e-10, 1e-4):
+        tk.solve_dual(K, y, wl.lambdas[-2:], tol=tol)   # warm the plan caches
+        (alpha, infos), dt = timed(lambda: tk.solve_dual(K, y, wl.lambdas, tol=tol))
+        f1 = f1_of(alpha)
+        rec = {"seconds": dt, "passes": sum(i["passes"] + i["hess_passes"] for i in infos),
+               "newton_iters": sum(i["newton_iters"] for i in infos),
+               "all_converged": all(i["status"] == 0 for i in infos),
+               "support_f1_min": min(f1), "support_f1_mean": float(np.mean(f1))}
+        # the same 64 lambdas as independent cold FP64 solves: the speedup of
+        # the batched form at equal support accuracy
+        A, di = timed(lambda: torch.cat([tk.solve_dual(K, y, [lam], tol=tol)[0] for lam in wl.lambdas]))
+        fi = f1_of(A)
+        rec["independent_fp64"] = {"seconds": di, "support_f1_min": min(fi), "speedup_of_path": di / dt}
+        out[f"tol_{tol:g}"] = rec
+    # reduced-precision storage along the path, finished on the FP64 tensor
+    # (without the FP64 finish these solves do not converge at small lambda)
+    for dtype in ("f32", "bf16"):
+        Kr = tk.build_packed_tensor(X, wl.m, dtype=dtype)
+        (alpha, infos), dr = timed(lambda: tk.solve_dual(Kr, y, wl.lambdas, tol=1e-4, polish=K))
+        fr = f1_of(alpha)
+        out["tol_0.0001"][f"{dtype}_storage_fp64_polish"] = {
+            "seconds": dr, "all_converged": all(i["status"] == 0 for i in infos), "support_f1_min": min(fr),
+            "speedup_vs_fp64_path": out["tol_0.0001"]["seconds"] / dr}
+        del Kr
     del K
     return out
 

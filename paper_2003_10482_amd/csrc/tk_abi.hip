@@ -645,6 +645,12 @@ double quartic_step(double s1, double s2, double f3, double f4)
 struct Precond {
     bool dev = false;
     bool ident = false;   // ... and that inverse is I / lambda' (from J = 0 at alpha = 0)
+    // the device Hessian slot b holds J at an iterate this far (sum of the
+    // accepted steps' lengths) from the current one; J does not depend on
+    // lambda, so it carries along a path
+    bool have_J = false;
+    double moved = 0.0;
+    double jtrace = 0.0;   // trace of the last J factored on the host (a bound on ||J||)
 };
 
 struct ProblemState {
@@ -746,6 +752,7 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
             TK_HIP_CHECK(hipStreamSynchronize(st));
             double tr = 0.0;
             for (int64_t i = 0; i < n; ++i) tr += std::fabs(A[i * n + i]);
+            pc[b].jtrace = tr;
             double shift = ps[b].lam;
             bool ok = false;
             for (int attempt = 0; attempt < 40 && !ok; ++attempt) {
@@ -772,6 +779,8 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
     const int phases = (dtype != TK_F64 && o.polish_K) ? 2 : 1;
     int rc = TK_OK;
     for (int phase = 0; phase < phases; ++phase) {
+        if (phase == 1)   // the polish may restart from another iterate
+            for (int64_t b = 0; b < B; ++b) pc[b].have_J = false;
         const void *Kp = phase == 0 ? K : o.polish_K;
         const int dt = phase == 0 ? dtype : TK_F64;
         const int hv_mode = dt == TK_F64 ? ACC_PLAIN64 : ACC_PLAIN32;
@@ -871,7 +880,17 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                     if (ps[b].done) continue;
                     // at alpha = 0 the Hessian of an order m >= 4 dual term is zero
                     const bool zero = !(ps[b].an > 0) && m >= 4;
-                    if ((rc = assemble(Kp, dt, b, zero))) return rc;
+                    // J from a nearby iterate still serves as the Newton operator
+                    // (convergence is decided on exact gradients) while its change,
+                    // about (m-2) ||J|| moved / ||alpha|| for a J homogeneous of
+                    // degree m-2, stays below lambda / 10
+                    const bool reuse = pc[b].have_J && !zero && pc[b].jtrace > 0 &&
+                                       (double)(m - 2) * pc[b].jtrace * pc[b].moved <= 0.1 * ps[b].lam * ps[b].an;
+                    if (!reuse) {
+                        if ((rc = assemble(Kp, dt, b, zero))) return rc;
+                        pc[b].have_J = !zero;
+                        pc[b].moved = 0.0;
+                    }
                     if (!pc[b].dev || (pc[b].ident && !zero) || ps[b].last_cg > refresh)
                         if ((rc = refresh_inverse(b, zero))) return rc;
                 }
@@ -959,6 +978,8 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                 }
                 TK_HIP_CHECK(vec_lin2(sb.x, sb.grad, c1, c2, sb.x, B, n, st));
             }
+            std::vector<double> xnorm(B);
+            for (int64_t b = 0; b < B; ++b) xnorm[b] = hr[b] > 0 ? std::sqrt(hr[b]) : INFINITY;
             // slope = grad . x
             TK_HIP_CHECK(vec_dot(sb.grad, sb.x, n, sb.stats, B, n, st));
             std::vector<double> slope(B), t(B, 1.0);
@@ -1025,6 +1046,7 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                         s.D = Dn;
                         s.newton++;
                         last_t[b] = t[b];
+                        pc[b].moved += t[b] * xnorm[b];
                     } else {
                         t[b] *= 0.5;
                         if (t[b] < 1e-14) {   // no decrease visible: rounding floor of D
