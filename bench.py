@@ -51,9 +51,14 @@ KERNELS = {
 
 
 def source_digest(src: str) -> str:
+    """sha256 (first 16 hex digits) of the kernel's source and, for the
+    contraction passes, of the host code that sizes their grids."""
     import hashlib
-    with open(os.path.join(CSRC, src), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in (src, "tk_contract.hip") if src == "tk_pass.hpp" else (src,):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(kind: str):
