@@ -875,6 +875,7 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
             // ---- Hessians at the current iterates (the CG operator), and the
             // inverse preconditioner where none is held or the last Newton
             // step needed many CG steps
+            std::vector<bool> jfresh(B, false);   // J assembled at the current iterate
             if (use_pc) {
                 for (int64_t b = 0; b < B; ++b) {
                     if (ps[b].done) continue;
@@ -890,6 +891,7 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                         if ((rc = assemble(Kp, dt, b, zero))) return rc;
                         pc[b].have_J = !zero;
                         pc[b].moved = 0.0;
+                        jfresh[b] = true;
                     }
                     if (!pc[b].dev || (pc[b].ident && !zero) || ps[b].last_cg > refresh)
                         if ((rc = refresh_inverse(b, zero))) return rc;
@@ -987,22 +989,39 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
             bool need_model = false;   // the model pass is skipped once every problem takes unit steps
             for (int64_t b = 0; b < B; ++b)
                 if (!ps[b].done && !(std::fabs(last_t[b] - 1.0) <= 0.05)) need_model = true;
+            // m = 4 on FP64 storage with plain gradients and J fresh at alpha:
+            // the contraction along the line is the cubic
+            //   K (alpha + t x)^3 = g + t J x + t^2 (3 K x^2 alpha) + t^3 K x^3,
+            // so one directional-derivative pass at x along alpha (which also
+            // returns K x^3) replaces the gradient passes of the line search
+            bool algebraic = false;
             if (use_pc && (m == 2 || m == 4) && need_model) {
                 // exact model of D along x: s2 from the assembled Hessian, and
-                // for m = 4 the cubic and quartic terms from one plain pass
-                // gt = K . x^3 (D is a quartic polynomial in the step length)
+                // for m = 4 the cubic and quartic terms from one pass giving
+                // dv = K . x^3 (D is a quartic polynomial in the step length)
+                algebraic = m == 4 && dt == TK_F64 && !accurate && !o.polish_K;
+                for (int64_t b = 0; b < B; ++b)
+                    if (!ps[b].done && !jfresh[b]) algebraic = false;
                 std::vector<double> s2(B), f3(B, 0.0), f4(B, 0.0);
-                TK_HIP_CHECK(vec_symv(sb.Jd, sb.x, sb.hd, B, n, st));
+                TK_HIP_CHECK(vec_symv(sb.Jd, sb.x, sb.z, B, n, st));                 // z = J x
+                TK_HIP_CHECK(vec_lin2(sb.z, sb.z, one, zero, sb.hd, B, n, st));
                 TK_HIP_CHECK(vec_shift_dot(sb.x, sb.hd, lam, sb.stats, B, n, st));
                 if ((rc = sync_copy(s2.data(), sb.stats, B))) return rc;
                 if (m == 4) {
-                    const int pm = dt == TK_F64 ? ACC_PLAIN64 : ACC_PLAIN32;
-                    if ((rc = run_contract(Kp, dt, n, m, sb.x, nullptr, B, sb.gt, nullptr, pm, sb.cw, sb.cw_bytes, st)))
-                        return rc;
+                    if (algebraic) {   // r = 3 K x^2 alpha, dv = K x^3
+                        if ((rc = run_contract(Kp, dt, n, m, sb.x, alpha, B, sb.dv, sb.r, ACC_PLAIN64, sb.cw,
+                                               sb.cw_bytes, st)))
+                            return rc;
+                    } else {
+                        const int pm = dt == TK_F64 ? ACC_PLAIN64 : ACC_PLAIN32;
+                        if ((rc = run_contract(Kp, dt, n, m, sb.x, nullptr, B, sb.dv, nullptr, pm, sb.cw, sb.cw_bytes,
+                                               st)))
+                            return rc;
+                    }
                     passes++;
-                    TK_HIP_CHECK(vec_dot(alpha, sb.gt, n, sb.stats, B, n, st));
+                    TK_HIP_CHECK(vec_dot(alpha, sb.dv, n, sb.stats, B, n, st));
                     if ((rc = sync_copy(f3.data(), sb.stats, B))) return rc;
-                    TK_HIP_CHECK(vec_dot(sb.x, sb.gt, n, sb.stats, B, n, st));
+                    TK_HIP_CHECK(vec_dot(sb.x, sb.dv, n, sb.stats, B, n, st));
                     if ((rc = sync_copy(f4.data(), sb.stats, B))) return rc;
                 }
                 for (int64_t b = 0; b < B; ++b)
@@ -1020,7 +1039,13 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                 }
                 if (!anyls) break;
                 TK_HIP_CHECK(vec_lin2(alpha, sb.x, one, tc, sb.at, B, n, st));   // at = alpha + t x
-                if ((rc = gradient(Kp, dt, sb.at, sb.gt, sb.hd, hst))) return rc;
+                if (algebraic) {   // gt = g + t J x + t^2 r + t^3 dv
+                    TK_HIP_CHECK(vec_poly3(sb.g, sb.z, sb.r, sb.dv, tc, sb.gt, B, n, st));
+                    TK_HIP_CHECK(vec_grad(sb.gt, sb.at, y, lam, sb.hd, sb.stats, B, n, st));
+                    if ((rc = sync_copy(hst.data(), sb.stats, B * 4))) return rc;
+                } else if ((rc = gradient(Kp, dt, sb.at, sb.gt, sb.hd, hst))) {
+                    return rc;
+                }
                 Coefs acc_c{}, keep_c{};
                 bool anyacc = false;
                 for (int64_t b = 0; b < B; ++b) {

@@ -195,8 +195,18 @@ __global__ __launch_bounds__(256) void hess_tri_reduce(const double *__restrict_
     const int L = (k1 - k0) * (2 * n - k0 - k1 + 1) / 2;
     const int pos = blockIdx.x * blockDim.x + threadIdx.x;
     if (pos >= L) return;
-    double s = 0.0;
-    for (int i = tile_items[t]; i < tile_items[t + 1]; ++i) s += part[(int64_t)i * kHessL + pos];
+    // eight independent partial sums keep eight loads in flight per thread
+    // (the sum order is fixed, so the result stays reproducible)
+    const int i0 = tile_items[t], i1 = tile_items[t + 1];
+    double s8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int i = i0;
+    for (; i + 8 <= i1; i += 8)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s8[u] += part[(int64_t)(i + u) * kHessL + pos];
+#pragma unroll
+    for (int u = 0; u < 7; ++u)
+        if (i + u < i1) s8[u] += part[(int64_t)(i + u) * kHessL + pos];
+    const double s = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
     U[(int64_t)k0 * (2 * n - k0 + 1) / 2 + pos] = s;
 }
 

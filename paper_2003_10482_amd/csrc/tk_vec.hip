@@ -243,6 +243,19 @@ __global__ void __launch_bounds__(256) cg_dense_kernel(const double *__restrict_
     if (i == 0) steps[b] = it;
 }
 
+// z_b = g_b + t_b (a_b + t_b (c_b + t_b e_b)), a cubic in the step length.
+__global__ void __launch_bounds__(256) poly3_kernel(const double *__restrict__ g, const double *__restrict__ a,
+                                                    const double *__restrict__ c, const double *__restrict__ e,
+                                                    Coefs t, double *__restrict__ z, int64_t n)
+{
+    const int b = blockIdx.y;
+    const double tb = t.c[b];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = (int64_t)b * n + i;
+        z[j] = g[j] + tb * (a[j] + tb * (c[j] + tb * e[j]));
+    }
+}
+
 }  // namespace
 
 hipError_t vec_grad(const double *g, const double *alpha, const double *y, const Coefs &lam,
@@ -304,6 +317,14 @@ hipError_t vec_cg_dense(const double *J, const double *P, const double *grad, co
     if (n > 256) return hipErrorInvalidValue;
     hipLaunchKernelGGL(cg_dense_kernel, dim3((unsigned)B), dim3(256), 0, st, J, P, grad, lam, eta, act, (int)n, max_it,
                        x, steps);
+    return hipGetLastError();
+}
+
+hipError_t vec_poly3(const double *g, const double *a, const double *c, const double *e, const Coefs &t, double *z,
+                     int64_t B, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(poly3_kernel, dim3(grid_for(n) > 8 ? 8 : grid_for(n), (unsigned)B), dim3(256), 0, st, g, a, c,
+                       e, t, z, n);
     return hipGetLastError();
 }
 

@@ -29,6 +29,9 @@ hipError_t vec_nonfinite(const double *x, int64_t len, int *flag, hipStream_t st
 // workgroup per problem, n <= 256); steps[b] receives the CG steps taken.
 hipError_t vec_cg_dense(const double *J, const double *P, const double *grad, const Coefs &lam, const Coefs &eta,
                         const Coefs &act, int64_t B, int64_t n, int max_it, double *x, int *steps, hipStream_t st);
+// z_b = g_b + t_b a_b + t_b^2 c_b + t_b^3 e_b
+hipError_t vec_poly3(const double *g, const double *a, const double *c, const double *e, const Coefs &t, double *z,
+                     int64_t B, int64_t n, hipStream_t st);
 // z_b = A_b x_b (A_b symmetric [n][n], row-major)
 hipError_t vec_symv(const double *A, const double *x, double *z, int64_t B, int64_t n, hipStream_t st);
 
