@@ -23,19 +23,30 @@ __global__ void __launch_bounds__(256) reduce_partials_kernel(ReduceParams p)
     const int slot = threadIdx.x / cols;      // 32 slots
     const int b = blockIdx.y;
     const int l = blockIdx.x * cols + lane_col;
-    DD s{0.0, 0.0};
+    // four independent compensated chains per thread (workgroups w, w + 32,
+    // w + 64, w + 96 of each stride of 128) keep four loads in flight; the
+    // order is fixed, so the result stays reproducible
+    DD s4[4] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
     if (l < p.n) {
         for (int ps = 0; ps < p.npass; ++ps) {
             const double *src = p.part[ps] + 2 * ((int64_t)b * p.groups[ps]) * p.n;
-            for (int w = slot; w < p.groups[ps]; w += 32) {
-                const double *q = src + 2 * ((int64_t)w * p.n + l);
-                double t, e;
-                two_sum(s.hi, q[0], t, e);
-                s.hi = t;
-                s.lo += e + q[1];
+            const int G = p.groups[ps];
+            for (int w0 = slot; w0 < G; w0 += 128) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int w = w0 + 32 * u;
+                    if (w < G) {
+                        const double *q = src + 2 * ((int64_t)w * p.n + l);
+                        double t, e;
+                        two_sum(s4[u].hi, q[0], t, e);
+                        s4[u].hi = t;
+                        s4[u].lo += e + q[1];
+                    }
+                }
             }
         }
     }
+    const DD s = dd_add(dd_add(s4[0], s4[1]), dd_add(s4[2], s4[3]));
     sh_hi[threadIdx.x] = s.hi;
     sh_lo[threadIdx.x] = s.lo;
     __syncthreads();
