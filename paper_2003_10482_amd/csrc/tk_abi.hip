@@ -1002,11 +1002,12 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                 algebraic = m == 4 && dt == TK_F64 && !accurate && !o.polish_K;
                 for (int64_t b = 0; b < B; ++b)
                     if (!ps[b].done && !jfresh[b]) algebraic = false;
-                std::vector<double> s2(B), f3(B, 0.0), f4(B, 0.0);
+                // s2, f3, f4 land in three slices of the statistics buffer and
+                // reach the host in one copy
+                std::vector<double> mod(3 * B, 0.0);
                 TK_HIP_CHECK(vec_symv(sb.Jd, sb.x, sb.z, B, n, st));                 // z = J x
                 TK_HIP_CHECK(vec_lin2(sb.z, sb.z, one, zero, sb.hd, B, n, st));
                 TK_HIP_CHECK(vec_shift_dot(sb.x, sb.hd, lam, sb.stats, B, n, st));
-                if ((rc = sync_copy(s2.data(), sb.stats, B))) return rc;
                 if (m == 4) {
                     if (algebraic) {   // r = 3 K x^2 alpha, dv = K x^3
                         if ((rc = run_contract(Kp, dt, n, m, sb.x, alpha, B, sb.dv, sb.r, ACC_PLAIN64, sb.cw,
@@ -1019,13 +1020,14 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                             return rc;
                     }
                     passes++;
-                    TK_HIP_CHECK(vec_dot(alpha, sb.dv, n, sb.stats, B, n, st));
-                    if ((rc = sync_copy(f3.data(), sb.stats, B))) return rc;
-                    TK_HIP_CHECK(vec_dot(sb.x, sb.dv, n, sb.stats, B, n, st));
-                    if ((rc = sync_copy(f4.data(), sb.stats, B))) return rc;
+                    TK_HIP_CHECK(vec_dot(alpha, sb.dv, n, sb.stats + B, B, n, st));
+                    TK_HIP_CHECK(vec_dot(sb.x, sb.dv, n, sb.stats + 2 * B, B, n, st));
+                    if ((rc = sync_copy(mod.data(), sb.stats, 3 * B))) return rc;
+                } else if ((rc = sync_copy(mod.data(), sb.stats, B))) {
+                    return rc;
                 }
                 for (int64_t b = 0; b < B; ++b)
-                    if (!ps[b].done) t[b] = quartic_step(slope[b], s2[b], f3[b], f4[b]);
+                    if (!ps[b].done) t[b] = quartic_step(slope[b], mod[b], mod[B + b], mod[2 * B + b]);
             }
             std::vector<bool> ls(B);
             for (int64_t b = 0; b < B; ++b) ls[b] = !ps[b].done;
