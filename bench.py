@@ -4,10 +4,13 @@ One step = one pass of the whole hot path on the workload n=256, d=200, m=4,
 lambda=1e-2 (synthetic, Section 5.4 data model, seed 1002), inputs resident in
 HBM: build the packed FP64 tensor (C(259,4) = 183,181,376 entries, 1.47 GB),
 solve the dual to ||grad D|| <= 1e-11 lambda ||alpha|| with the Newton solver
-(compensated gradient and line-search passes over the packed tensor; the
-Hessian assembled in two passes at every Newton step, CG on the dense
-system), recover w = (X^T alpha)^3, take the 2-std support and predict on X.
-After the timed steps, the 64-value lambda path of the same data is solved
+(the Hessian assembled in two passes at every Newton step, CG on the dense
+system, the step length and the line search's gradients from one
+directional-derivative pass, compensated gradient passes for the last
+steps), recover w = (X^T alpha)^3, take the 2-std support and predict on X.
+After the timed steps, the contraction alone is timed ("contraction": one
+vector, plain and compensated, and a batch of 64 with the autotuned tile),
+and the 64-value lambda path of the same data is solved
 and timed separately ("lambda_path"): by continuation, as 64 independent
 cold solves (the batched form's speedup at equal support accuracy), and
 with FP32/BF16 storage finished on the FP64 tensor.
@@ -191,6 +194,40 @@ def lambda_path(tk, torch, dev) -> dict:
     return out
 
 
+def contraction_rates(tk, torch, dev, K, n: int) -> dict:
+    """The contraction K . alpha^{m-1} alone on the benchmark tensor, outside
+    the timed steps: one vector with plain and with compensated FP64
+    accumulation, and a batch of 64 vectors (the lambda-path shape) with the
+    vector tile the autotuner picks.  HIP events per launch; GB/s counts the
+    tensor bytes per read (a tile of t vectors shares one read)."""
+    g = torch.Generator(device="cpu").manual_seed(11)
+    a1 = (0.1 * torch.randn(1, n, generator=g, dtype=torch.float64)).to(dev)
+    a64 = (0.1 * torch.randn(64, n, generator=g, dtype=torch.float64)).to(dev)
+    tile, _, _ = tk.autotune(K, a64, acc=tk.ACC_F64)
+    out = {}
+    for name, alpha, acc, kind, vectors in (("one_vector_plain_fp64", a1, tk.ACC_F64, "contract_plain", 1),
+                                             ("one_vector_compensated_fp64", a1, tk.ACC_COMPENSATED, "contract", 1),
+                                             ("batch_64_plain_fp64", a64, tk.ACC_F64, "contract_plain", 64)):
+        for _ in range(3):
+            tk.contract(K, alpha, acc=acc)
+        torch.cuda.synchronize()
+        tk.timing_start()
+        reps = 20 if vectors == 1 else 4
+        for _ in range(reps):
+            tk.contract(K, alpha, acc=acc)
+        torch.cuda.synchronize()
+        launches, ms, nbytes = tk.timing_stop()[kind]
+        avg = ms / launches
+        rec = {"ms_per_launch": avg, "contractions_per_s": vectors / (avg * 1e-3),
+               "hbm_GBs": (nbytes / launches) / (avg * 1e-3) / 1e9,
+               "frac_of_peak": (nbytes / launches) / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        if vectors > 1:
+            rec["vector_tile"] = tile
+            rec["effective_GBs"] = vectors * K.count * 8 / (avg * 1e-3) / 1e9
+        out[name] = rec
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -286,6 +323,9 @@ def main() -> int:
                                      "achieved_GBs": (b / l) / (ms / l * 1e-3) / 1e9}
                                  for k, (l, ms, b) in ran.items()}},
     }
+    K = tk.build_packed_tensor(X, wl.m, dtype="f64")
+    out["contraction"] = contraction_rates(tk, torch, dev, K, wl.n)
+    del K
     if not args.no_path:
         out["lambda_path"] = lambda_path(tk, torch, dev)
     if not args.no_cpu_baseline:
