@@ -64,6 +64,25 @@ def test_solve_config1_matches_oracle():
     assert np.array_equal(to_np(mask), mref)
 
 
+@pytest.mark.parametrize("m", [4, 6])
+def test_solve_without_assembled_hessian(m):
+    """precond=False: truncated Newton with unpreconditioned CG whose products
+    are directional-derivative passes over the tensor (no Hessian kernel),
+    backtracking line search; same optimum as the default solver."""
+    wl = make_workload("c1_n64_m4")
+    X, y = to_dev(wl.X), to_dev(wl.y)
+    K = tk.build_packed_tensor(X, m)
+    a1, i1 = tk.solve_dual(K, y, [wl.lam], tol=1e-11, precond=False)
+    a2, i2 = tk.solve_dual(K, y, [wl.lam], tol=1e-11)
+    assert i1[0]["status"] == 0 and i2[0]["status"] == 0, (i1, i2)
+    assert i1[0]["hess_passes"] == 0 and i2[0]["hess_passes"] > 0
+    ref, _ = D.solve_linear(wl.X, wl.y, wl.lam, m)
+    w_ref = D.primal_from_dual(wl.X, ref, m)
+    for a in (a1, a2):
+        w = to_np(tk.primal_weights(X, a[0], m))
+        assert np.linalg.norm(w - w_ref) <= 1e-8 * np.linalg.norm(w_ref)
+
+
 @pytest.mark.parametrize("lam", [1.0, 1e-1])
 def test_solve_order2_is_krr(lam):
     rng = np.random.default_rng(5)
