@@ -661,10 +661,17 @@ struct ProblemState {
     bool done;
 };
 
-// One batch (B <= kMaxCoefs) of dual solves.  Newton direction from CG on
-// (J + lambda I) p = -grad (truncated with an Eisenstat-Walker forcing term),
-// Armijo backtracking on D.  Gradients: compensated FP64 on FP64 storage,
-// otherwise FP32 accumulation; the optional polish continues on an FP64 tensor.
+// One batch (B <= kMaxCoefs) of dual solves.  Each Newton step: the Hessian
+// J assembled at alpha (two reads of the tensor; reused while its change stays
+// below lambda / 10), CG on the dense system (J + lambda I) p = -grad on the
+// device (preconditioned with a host-factored inverse from an earlier
+// Hessian, truncated with an Eisenstat-Walker forcing term), the exact step
+// length along p for m = 2, 4 (D is a polynomial in the step), Armijo
+// backtracking as the safeguard.  Gradients: plain FP64 far from the optimum
+// on a cold start and compensated FP64 near it on FP64 storage, FP32
+// accumulation on reduced storage; the optional polish continues on an FP64
+// tensor.  precond = 0 runs unpreconditioned CG whose products are
+// directional-derivative passes over the tensor instead.
 int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, const double *lams, int64_t B,
                 const tk_solve_opts &o, double *alpha, tk_solve_info *info, SolveBuffers &sb, hipStream_t st,
                 std::vector<Precond> &pc)
