@@ -650,7 +650,7 @@ struct Precond {
     // lambda, so it carries along a path
     bool have_J = false;
     double moved = 0.0;
-    double jtrace = 0.0;   // trace of the last J factored on the host (a bound on ||J||)
+    double jnorm = 0.0;   // Frobenius norm of the last J factored on the host (>= ||J||_2)
 };
 
 struct ProblemState {
@@ -757,9 +757,10 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
             TK_HIP_CHECK(hipMemcpyAsync(A.data(), sb.Jd + b * n * n, (size_t)n * n * sizeof(double),
                                         hipMemcpyDeviceToHost, st));
             TK_HIP_CHECK(hipStreamSynchronize(st));
-            double tr = 0.0;
+            double tr = 0.0, fro = 0.0;
             for (int64_t i = 0; i < n; ++i) tr += std::fabs(A[i * n + i]);
-            pc[b].jtrace = tr;
+            for (int64_t i = 0; i < n * n; ++i) fro += A[i] * A[i];
+            pc[b].jnorm = std::sqrt(fro);
             double shift = ps[b].lam;
             bool ok = false;
             for (int attempt = 0; attempt < 40 && !ok; ++attempt) {
@@ -892,8 +893,8 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                     // (convergence is decided on exact gradients) while its change,
                     // about (m-2) ||J|| moved / ||alpha|| for a J homogeneous of
                     // degree m-2, stays below lambda / 10
-                    const bool reuse = pc[b].have_J && !zero && pc[b].jtrace > 0 &&
-                                       (double)(m - 2) * pc[b].jtrace * pc[b].moved <= 0.1 * ps[b].lam * ps[b].an;
+                    const bool reuse = pc[b].have_J && !zero && pc[b].jnorm > 0 &&
+                                       (double)(m - 2) * pc[b].jnorm * pc[b].moved <= 0.1 * ps[b].lam * ps[b].an;
                     if (!reuse) {
                         if ((rc = assemble(Kp, dt, b, zero))) return rc;
                         pc[b].have_J = !zero;
