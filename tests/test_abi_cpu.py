@@ -73,3 +73,28 @@ def test_product_path_has_no_oracle_import():
             if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in re.sub(r"#.*|//.*", "", txt).replace("Oracle", ""), f
+
+
+def test_hessian_entry_points_on_host():
+    """tk_hessian_workspace is host arithmetic that grows with the order and
+    covers the unit vectors of m >= 4; tk_hessian rejects bad arguments
+    before any device work, and the binding rejects host tensors."""
+    import torch
+
+    import paper_2003_10482_amd as tk
+    from paper_2003_10482_amd import _lib
+    lib = _lib.load()
+    ws = ctypes.c_size_t()
+    assert lib.tk_hessian_workspace(256, 4, ctypes.byref(ws)) == 0
+    w4 = ws.value
+    # at least the order-3 array of unit vectors, C(258, 3) doubles
+    assert w4 >= 8 * 2829056
+    assert lib.tk_hessian_workspace(64, 2, ctypes.byref(ws)) == 0 and 0 < ws.value < w4
+    assert lib.tk_hessian_workspace(64, 3, ctypes.byref(ws)) == -1        # odd order
+    assert lib.tk_hessian_workspace(300, 4, ctypes.byref(ws)) == -7       # above the tile limit
+    assert lib.tk_hessian(None, 0, 64, 4, None, None, None, 0, None) == -1
+    assert lib.tk_hessian(ctypes.c_void_p(8), 7, 64, 4, ctypes.c_void_p(8), ctypes.c_void_p(8),
+                          ctypes.c_void_p(8), 1, None) == -1                # bad dtype
+    K = tk.PackedTensor(torch.zeros(tk.packed_count(5, 4), dtype=torch.float64), 5, 4, tk.F64)
+    with pytest.raises(ValueError):
+        tk.hessian(K, torch.zeros(5, dtype=torch.float64))
