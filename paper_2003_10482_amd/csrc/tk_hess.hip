@@ -37,8 +37,8 @@ namespace {
 
 constexpr int kHessJT = 16;                  // tile positions per lane
 constexpr int kHessL = kHessJT * kWave;      // upper-triangle entries per row tile (at most)
-constexpr int kHessItems = 2048;             // target work items of the tile kernel
-constexpr int kHessRWaves = 4096;            // target waves of the unit kernel
+constexpr int kHessItems = 4096;             // target work items of the tile kernel
+constexpr int kHessRWaves = 32768;           // target waves of the unit kernel
 constexpr int kHessXWaves = 4096;            // target waves of the cross kernel
 constexpr int kTB = kMaxOrder + 1;           // binomial table: C(a, b) for b < kTB
 
