@@ -235,6 +235,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-path", action="store_true", help="skip the 64-lambda path (outside the timed steps)")
+    ap.add_argument("--no-contraction", action="store_true",
+                    help="skip the standalone contraction timings (outside the timed steps)")
     ap.add_argument("--pass-only", type=int, default=0,
                     help="run only this many launches of one kernel (for counter runs)")
     ap.add_argument("--pass-kind", default="hvp", choices=sorted(KERNELS))
@@ -323,9 +325,10 @@ def main() -> int:
                                      "achieved_GBs": (b / l) / (ms / l * 1e-3) / 1e9}
                                  for k, (l, ms, b) in ran.items()}},
     }
-    K = tk.build_packed_tensor(X, wl.m, dtype="f64")
-    out["contraction"] = contraction_rates(tk, torch, dev, K, wl.n)
-    del K
+    if not args.no_contraction:
+        K = tk.build_packed_tensor(X, wl.m, dtype="f64")
+        out["contraction"] = contraction_rates(tk, torch, dev, K, wl.n)
+        del K
     if not args.no_path:
         out["lambda_path"] = lambda_path(tk, torch, dev)
     if not args.no_cpu_baseline:
