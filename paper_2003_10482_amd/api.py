@@ -109,6 +109,8 @@ def contract(K: PackedTensor, alpha: torch.Tensor, acc: int = ACC_AUTO,
     a2 = alpha.reshape(-1, K.n)
     B = a2.shape[0]
     g = torch.empty_like(a2) if out is None else out
+    if B == 0:   # an empty batch: nothing to compute
+        return g.reshape(alpha.shape)
     if work is None:
         work = _workspace(contract_workspace(K.n, K.m, B, K.dtype), alpha.device)
     _lib.check(_lib.load().tk_contract(_ptr(K.data), K.dtype, K.n, K.m, _ptr(a2), B, _ptr(g), acc,
@@ -128,6 +130,8 @@ def hvp(K: PackedTensor, alpha: torch.Tensor, v: torch.Tensor, with_g: bool = Fa
     B = a2.shape[0]
     h = torch.empty_like(a2)
     g = torch.empty_like(a2) if with_g else None
+    if B == 0:   # an empty batch: nothing to compute
+        return (h.reshape(alpha.shape), g.reshape(alpha.shape)) if with_g else h.reshape(alpha.shape)
     if work is None:
         work = _workspace(contract_workspace(K.n, K.m, B, K.dtype), alpha.device)
     _lib.check(_lib.load().tk_hvp(_ptr(K.data), K.dtype, K.n, K.m, _ptr(a2), _ptr(v2), B, _ptr(h), _ptr(g),

@@ -868,7 +868,9 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                         s.done = true;   // running off on the rounded tensor
                     }
                 }
-                if (!s.done && o.fixed_iters <= 0 && s.gn <= tol * s.lam * s.an && s.an > 0) s.done = true;
+                // an exactly zero gradient is the optimum (y = 0 gives alpha = 0)
+                if (!s.done && o.fixed_iters <= 0 && (s.gn == 0 || (s.gn <= tol * s.lam * s.an && s.an > 0)))
+                    s.done = true;
                 if (!s.done && phases == 2 && phase == 0) {
                     if (s.gn < 0.5 * best_gn[b]) {
                         best_gn[b] = s.gn;

@@ -299,3 +299,25 @@ def test_memory_past_the_tensor_is_not_read(n, m, storage):
     for a, b in zip(res[0], res[1]):
         assert np.all(np.isfinite(b))
         np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("n,m", [(70, 4), (13, 6), (30, 2)])
+def test_empty_batch_and_zero_vector(n, m):
+    """Degenerate inputs: an empty batch of vectors gives an empty result (no
+    launch); alpha = 0 gives g = 0 and h = 0 exactly (every term of the sum
+    has a factor alpha_i), for every accumulation mode."""
+    Kh = random_symmetric_packed_values(tk.packed_count(n, m), seed=n + m)
+    K, _ = _packed_dev(Kh, n, m)
+    empty = torch.zeros(0, n, dtype=torch.float64, device=device())
+    assert tuple(tk.contract(K, empty).shape) == (0, n)
+    h, g = tk.hvp(K, empty, empty, with_g=True)
+    assert tuple(h.shape) == (0, n) and tuple(g.shape) == (0, n)
+    zero = torch.zeros(2, n, dtype=torch.float64, device=device())
+    for acc in (tk.ACC_F64, tk.ACC_COMPENSATED):
+        assert not to_np(tk.contract(K, zero, acc=acc)).any()
+    v = to_dev(random_alpha(n, seed=4, batch=2))
+    h = to_np(tk.hvp(K, zero, v, acc=tk.ACC_COMPENSATED))
+    if m == 2:   # h = K v, independent of alpha
+        assert np.all(np.isfinite(h))
+    else:
+        assert not h.any()

@@ -152,3 +152,20 @@ def test_autograd_backward_is_hvp():
     (out * gvec).sum().backward()
     ref = T.hvp_closed(X, to_np(a.detach()), to_np(gvec), m)
     np.testing.assert_allclose(to_np(a.grad), ref, rtol=1e-10, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("m", [2, 4, 6])
+def test_solve_zero_targets(m):
+    """y = 0: the dual objective (strictly convex for lambda > 0) has its
+    minimum at alpha = 0, where the gradient is exactly zero, so the solve
+    stops there at once, for every lambda and storage type."""
+    rng = np.random.default_rng(9)
+    X = rng.standard_normal((40, 8))
+    y = np.zeros(40)
+    lams = [1.0, 1e-2, 1e-4]
+    for dtype in ("f64", "f32"):
+        K = tk.build_packed_tensor(to_dev(X), m, dtype=dtype)
+        alpha, infos = tk.solve_dual(K, to_dev(y), lams)
+        assert not to_np(alpha).any()
+        for inf in infos:
+            assert inf["status"] == 0 and inf["newton_iters"] == 0, inf
