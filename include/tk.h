@@ -25,6 +25,15 @@
  *        D(alpha) = (1/m) <K, alpha^{(x)m}> + (lambda/2)||alpha||^2 - <y, alpha>.
  *  - Calls that share a workspace must not overlap in time; distinct
  *    workspaces may be used concurrently on different streams.
+ *  - Non-finite values: the asynchronous entry points do not inspect the
+ *    values they are given (that would need a synchronisation); a NaN or Inf
+ *    input propagates into the outputs by IEEE arithmetic.  The synchronous
+ *    entry points (tk_solve_dual, tk_dmse_dlambda) check their vector and
+ *    matrix inputs first and return TK_ENAN before any pass.
+ *  - Reproducibility: reductions run in a fixed order for a given launch
+ *    shape, and launch shapes follow the device's compute-unit count and the
+ *    kernels' occupancy, so results are bitwise reproducible per (device
+ *    model, n, m, B, dtype, acc, vector tile), not across device models.
  */
 #ifndef TK_H
 #define TK_H
@@ -102,9 +111,11 @@ int tk_contract_workspace(int64_t n, int m, int64_t B, int dtype, size_t *h_byte
 /*
  * g = K . alpha^{m-1} for B vectors:  g_b[a] = sum_{i_2..i_m} K[a,i_2..i_m] alpha_b[i_2]..alpha_b[i_m]
  * (the gradient of the first term of eq. dual_tensor_kernel).  The packed
- * array d_K (dtype) is streamed once per pass; alpha and g are FP64 [B*n].
- * `acc` selects the accumulation (tk_acc).  The reduction order is fixed, so
- * results are bitwise reproducible for a given (n, m, B, dtype, acc).
+ * array d_K (dtype) is streamed once per tile of vectors: a workgroup applies
+ * each entry it loads to a tile of 1, 2 or 4 vectors (tk_autotune picks the
+ * tile), so a batch of B vectors reads K ceil(B / tile) times.  alpha and g
+ * are FP64 [B*n].  `acc` selects the accumulation (tk_acc).  The reduction
+ * order is fixed for a launch shape (see the reproducibility convention).
  * Errors: TK_EINVAL, TK_ENOMEM (work_bytes too small), TK_EUNSUPPORTED, TK_EHIP.
  */
 int tk_contract(const void *d_K, int dtype, int64_t n, int m, const double *d_alpha,
@@ -162,6 +173,15 @@ int tk_autotune(const void *d_K, int dtype, int64_t n, int m, const double *d_al
                 const double *d_v, int64_t B, int acc, double *d_out, void *d_work,
                 size_t work_bytes, void *stream, int *h_tile, double *h_ms);
 
+/* Loss of the primal problem (eq. tensor_infinite_2); the dual replaces it by
+ * its Fenchel conjugate (Section 4). */
+typedef enum {
+    TK_LOSS_SQUARE = 0,   /* L(y, t) = (y - t)^2 / 2: the dual of eq. dual_tensor_kernel */
+    TK_LOSS_LOGISTIC = 1  /* L(y, t) = log(1 + exp(-y t)), y in {-1, +1}: the dual term
+                             (1/lambda) sum_i [p_i log p_i + (1 - p_i) log(1 - p_i)],
+                             p_i = lambda y_i alpha_i in (0, 1) */
+} tk_loss;
+
 /* Options of the dual solve (host struct). */
 typedef struct {
     int max_newton;      /* Newton iterations per lambda (default 100) */
@@ -188,7 +208,31 @@ typedef struct {
                             largest down, each started from the previous solution and keeping
                             its preconditioner; 0: all lambdas in lock step, sharing every
                             pass */
+    int loss;            /* tk_loss (default TK_LOSS_SQUARE).  The logistic loss starts cold
+                            solves at the centre of the dual's domain (p_i = 1/2), keeps every
+                            step inside it (at most 0.99 of the way to its boundary) and
+                            backtracks on D; the Newton operator is J + diag(lambda / (p (1-p))) */
+    int support_stop;    /* > 0 (linear tensor kernel only): also stop a lambda once the
+                            2-std support of w = (X^T alpha)^{m-1} (Section 6.3 threshold, as
+                            tk_support) has stayed the same for this many consecutive Newton
+                            steps; info.stop_reason records it.  0 (default): off */
+    const double *support_X; /* device [n*support_d]: the points the tensor was built from */
+    int64_t support_d;
 } tk_solve_opts;
+
+/* Why a solve that returned TK_OK stopped. */
+typedef enum {
+    TK_STOP_TOL = 0,     /* ||grad D|| <= tol * lambda * ||alpha|| (or an exactly zero gradient) */
+    TK_STOP_SUPPORT = 1, /* the stable-support rule (opts.support_stop) */
+    TK_STOP_FLOOR = 2    /* reduced-precision storage without a polish tensor: the gradient
+                            stopped falling at the noise floor of the storage rounding (no
+                            halving in 3 Newton steps, or growth 1000x past its best); the
+                            iterate of smallest gradient is returned and grad_norm is its
+                            reduced-precision gradient.  By lambda-strong convexity the
+                            error of alpha is at most ||grad D(alpha)|| / lambda with the
+                            gradient of the FP64 problem, which a caller holding the FP64
+                            tensor can evaluate with tk_contract */
+} tk_stop_reason;
 
 typedef struct {
     int newton_iters;
@@ -202,11 +246,14 @@ typedef struct {
     int hess_passes;     /* passes over the packed tensor spent on Hessian assembly (two per
                             Hessian, one for m = 2) */
     int precond_updates; /* preconditioner factorisations for this lambda */
+    int stop_reason;     /* with status TK_OK: what ended this lambda (tk_stop_reason) */
 } tk_solve_info;
 
 void tk_solve_opts_default(tk_solve_opts *h_opts);
 
 int tk_solve_workspace(int64_t n, int m, int64_t B, int dtype, size_t *h_bytes);
+/* Workspace of tk_solve_dual with opts->support_stop > 0 (points of dimension support_d). */
+int tk_solve_workspace_ex(int64_t n, int m, int64_t B, int dtype, int64_t support_d, size_t *h_bytes);
 
 /*
  * Minimise the dual D(alpha) of eq. dual_tensor_kernel for B regularisation
@@ -218,12 +265,55 @@ int tk_solve_workspace(int64_t n, int m, int64_t B, int dtype, size_t *h_bytes);
  * holds B values (host); d_alpha [B*n] receives the solutions (and holds the
  * warm start when opts->warm_start).  h_info receives B records.
  * Synchronises: returns when every lambda has converged or hit its limits.
- * Returns TK_OK when all converged, TK_ENOCONV if any did not (check h_info).
+ * Returns TK_OK when all converged, TK_ENOCONV if any did not (check h_info),
+ * TK_ENAN when d_y (or the warm start) holds a NaN or Inf (checked before any
+ * pass; outputs untouched) or an iterate became non-finite.
  */
 int tk_solve_dual(const void *d_K, int dtype, int64_t n, int m, const double *d_y,
                   const double *h_lambdas, int64_t B, const tk_solve_opts *h_opts,
                   double *d_alpha, tk_solve_info *h_info, void *d_work, size_t work_bytes,
                   void *stream);
+
+/*
+ * Several packed tensors of the same (n, m, dtype) side by side: tensor t
+ * starts k_stride entries after tensor t-1.  tk_packed_stride gives the
+ * smallest stride that keeps every tensor 256-byte aligned (C(n+m-1, m)
+ * rounded up); any larger stride with 16-byte alignment is accepted.  This is
+ * the layout of the subsample grid of Section 6.1: T random draws of n
+ * landmarks each, one tensor per draw.
+ */
+int tk_packed_stride(int64_t n, int m, int dtype, int64_t *h_stride);
+
+/* Build T tensors: d_X [T*n*d] (draw t's points from row t*n), d_K [T*k_stride]. */
+int tk_build_packed_multi(const double *d_X, int64_t T, int64_t n, int64_t d, int m, int kernel,
+                          double kparam, int dtype, void *d_K, int64_t k_stride, void *stream);
+
+/*
+ * g_t = K_t . alpha_t^{m-1} for T tensors in one launch per pass (vector t
+ * contracts tensor t; each tensor is read once).  d_alpha, d_g [T*n];
+ * workspace tk_contract_workspace(n, m, T, dtype).  Errors: as tk_contract.
+ */
+int tk_contract_multi(const void *d_K, int dtype, int64_t n, int m, int64_t T, int64_t k_stride,
+                      const double *d_alpha, double *d_g, int acc, void *d_work, size_t work_bytes,
+                      void *stream);
+
+/*
+ * The (subsample, lambda) grid of Section 6.1: the dual of each of T tensors
+ * (draws) for each of L regularisation values.  The draws of one lambda are
+ * solved in lock step (up to 64 per batch: every pass over the tensors is one
+ * launch for the batch), the lambdas by continuation from the largest down,
+ * each draw keeping its own Hessian and preconditioner from lambda to lambda.
+ * d_y [T*n] (draw t's responses from t*n); d_alpha [L*T*n] receives the
+ * solutions, lambda-major: d_alpha[(l*T + t)*n + i]; h_info [L*T] the same
+ * order.  opts as tk_solve_dual (no polish tensor, no support_stop; loss
+ * allowed).  Workspace: tk_solve_workspace(n, m, min(T, 64), dtype).
+ * Synchronises.  Returns TK_OK when every problem converged, else TK_ENOCONV /
+ * TK_ENAN (check h_info).
+ */
+int tk_solve_dual_multi(const void *d_K, int dtype, int64_t n, int m, int64_t T, int64_t k_stride,
+                        const double *d_y, const double *h_lambdas, int64_t L,
+                        const tk_solve_opts *h_opts, double *d_alpha, tk_solve_info *h_info,
+                        void *d_work, size_t work_bytes, void *stream);
 
 /*
  * Primal weights of the linear tensor kernel (eq. tensor_representer with q = m
@@ -239,6 +329,28 @@ int tk_primal_weights(const double *d_X, int64_t n, int64_t d, int m, const doub
  */
 int tk_predict(const double *d_W, int64_t d, int64_t B, const double *d_Xq, int64_t N,
                double *d_f, void *stream);
+
+/*
+ * Prediction with a general tensor kernel (Section 4: the model written
+ * through the kernel, for feature maps with no finite form):
+ *   f_b(x) = sum_{sorted (m-1)-tuples T of training points} c(T) alpha_b^T
+ *            k(x_{T_1}, .., x_{T_{m-1}}, x),   c(T) = (m-1)! / prod_v mult_v(T)!
+ * i.e. the sum over all ordered (m-1)-tuples grouped by their sorted form.
+ * kernel/kparam as in tk_build_packed_tensor (linear, eq. poly_tensor, exp).
+ * d_X [n*d] training points (or landmarks), d_alpha [B*n] dual vectors,
+ * d_Xq [N*d] query points -> d_f [B*N].  FP64 throughout: the inner products
+ * sum_j prod_{t in T} x_{t,j} xq_j run on FP64 MFMA tiles (64 tuples x 64
+ * points), the weighted sums over tuples in a fixed order.  Work grows as
+ * C(n+m-2, m-1) * N * d.  For the linear kernel tk_predict on the primal
+ * weights is the cheap route (same value in exact arithmetic).
+ * d_work: tk_predict_kernel_workspace bytes.
+ * Errors: TK_EINVAL (sizes, m odd or > 8, N > 65535*64, kernel/kparam),
+ * TK_EOVERFLOW, TK_ENOMEM (workspace too small), TK_EHIP.
+ */
+int tk_predict_kernel_workspace(int64_t n, int m, int64_t B, int64_t N, size_t *h_bytes);
+int tk_predict_kernel(const double *d_X, int64_t n, int64_t d, int m, int kernel, double kparam,
+                      const double *d_alpha, int64_t B, const double *d_Xq, int64_t N, double *d_f,
+                      void *d_work, size_t work_bytes, void *stream);
 
 /*
  * Dense shortcut of a finite feature map (linear kernel): g_b = X (X^T alpha_b)^{m-1},
@@ -272,6 +384,10 @@ int tk_gather_rows(const double *d_X, int64_t N, int64_t d, const int64_t *d_idx
  *   (J(alpha*) + lambda I) z = d MSE_val / d alpha,   dMSE/dlambda = -z^T alpha*.
  * CG on tk_hvp passes (rel. residual cg_tol).  Outputs on the host: h_mse,
  * h_dmse; d_z [n] (may be NULL) receives z.  Synchronises.
+ * Errors: TK_EINVAL, TK_ENOMEM, TK_EHIP; TK_ENAN when an input holds a NaN or
+ * Inf (checked before any pass) or the result is not finite; TK_ENOCONV when
+ * CG ends above cg_tol (max_cg reached or positive curvature lost) -- the
+ * outputs then hold the last CG iterate's values.
  */
 int tk_dmse_dlambda(const void *d_K, int dtype, int64_t n, int m, const double *d_X, int64_t d,
                     const double *d_alpha, double lambda, const double *d_Xval,
@@ -296,6 +412,17 @@ int tk_dmse_workspace(int64_t n, int m, int64_t d, int64_t nval, int dtype, size
 #define TK_TIMING_KINDS 5
 int tk_timing_start(void);
 int tk_timing_stop(int64_t *h_launches, double *h_ms, double *h_bytes);
+
+/*
+ * Instrumentation (not part of the method): a plain streaming read of `bytes`
+ * bytes (a positive multiple of 16, d_src 16-byte aligned) by `groups`
+ * workgroups of 256 threads, each thread keeping eight non-temporal 16-byte
+ * loads in flight.  d_sink [groups] receives one word per workgroup (a checksum that
+ * keeps the loads live).  Timed beside the kernels that stream the packed
+ * tensor, it gives the achievable HBM read rate of the device.
+ * Errors: TK_EINVAL, TK_EHIP.
+ */
+int tk_probe_stream_read(const void *d_src, int64_t bytes, uint64_t *d_sink, int groups, void *stream);
 
 #ifdef __cplusplus
 }

@@ -292,3 +292,129 @@ def dmse_dlambda_linear(X, alpha, lam: float, m: int, X_val, y_val) -> float:
     H = T.jacobian_closed(X, alpha, m) + lam * np.eye(alpha.size)
     z = np.linalg.solve(H, grad_alpha_val_mse(X, alpha, m, X_val, y_val))
     return -float(z @ alpha)
+
+
+# ---------------------------------------------------------------------------
+# General convex loss through the Fenchel conjugate (Section 4, the dual of
+# eq. tensor_infinite_2):
+#     Lambda(alpha) = (1/q) ||Phi_n^* alpha||_q^q + gamma sum_i L*(y_i, -alpha_i / gamma),
+# with (1/q) ||Phi_n^* alpha||_q^q = (1/m) <K, alpha^{(x)m}> (q = m) and
+# gamma = 1/lambda.  For the square loss L(y, t) = (y - t)^2 / 2 this is the
+# dual above.  The classification loss used here is the logistic loss
+# L(y, t) = log(1 + exp(-y t)), y in {-1, +1} (the text prints 1 + e^{-yf};
+# read as the logistic loss it names).  Its conjugate, with u = -s y:
+#     L*(y, s) = u log u + (1 - u) log(1 - u)   for u in [0, 1], +inf otherwise,
+# so the separable dual term is, with p_i = lambda y_i alpha_i in [0, 1],
+#     gamma L*(y_i, -alpha_i / gamma) = (1/lambda) [p_i log p_i + (1 - p_i) log(1 - p_i)].
+# ---------------------------------------------------------------------------
+
+def logistic_loss(y, t) -> np.ndarray:
+    """L(y, t) = log(1 + exp(-y t)), evaluated without overflow."""
+    return np.logaddexp(0.0, -np.asarray(y, dtype=np.float64) * np.asarray(t, dtype=np.float64))
+
+
+def logistic_conjugate(y, s) -> np.ndarray:
+    """L*(y, s) = sup_t (s t - L(y, t)) = u log u + (1 - u) log(1 - u), u = -s y,
+    +inf outside u in [0, 1] (0 log 0 = 0)."""
+    u = -np.asarray(s, dtype=np.float64) * np.asarray(y, dtype=np.float64)
+    out = np.full(u.shape, np.inf)
+    ok = (u >= 0) & (u <= 1)
+    uu = u[ok]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        a = np.where(uu > 0, uu * np.log(np.where(uu > 0, uu, 1.0)), 0.0)
+        b = np.where(uu < 1, (1 - uu) * np.log(np.where(uu < 1, 1 - uu, 1.0)), 0.0)
+    out[ok] = a + b
+    return out
+
+
+def logistic_dual_objective(g, alpha, y, lam: float, m: int) -> float:
+    """Lambda(alpha) from g = K . alpha^{m-1} (<K, alpha^{(x)m}> = alpha^T g)."""
+    alpha = np.asarray(alpha, dtype=np.float64)
+    sep = logistic_conjugate(y, -lam * alpha)          # L*(y_i, -alpha_i / gamma), gamma = 1/lam
+    return float(alpha @ g) / m + float(np.sum(sep)) / lam
+
+
+def logistic_dual_grad(g, alpha, y, lam: float) -> np.ndarray:
+    """d Lambda / d alpha = g + y log(p / (1 - p)), p = lam y alpha (inside the domain)."""
+    p = lam * np.asarray(y) * np.asarray(alpha)
+    return g + np.asarray(y) * (np.log(p) - np.log1p(-p))
+
+
+def logistic_dual_hess_diag(alpha, y, lam: float) -> np.ndarray:
+    """Second derivative of the separable term: lam / (p (1 - p))."""
+    p = lam * np.asarray(y) * np.asarray(alpha)
+    return lam / (p * (1.0 - p))
+
+
+def solve_dual_logistic(contract: Callable, jacobian: Callable, y, lam: float, m: int,
+                        alpha0: Optional[np.ndarray] = None, rtol: float = 1e-14,
+                        max_iter: int = 500) -> tuple:
+    """Damped Newton on the logistic dual, from the centre of the domain
+    (p_i = 1/2) unless alpha0 is given.  Each step solves (J + diag(h)) s = -grad
+    by Cholesky, is shortened to stay inside the domain (at most 0.99 of the way
+    to its boundary), then backtracked (Armijo).  Stops when ||grad|| <= rtol *
+    (||g|| + ||sep. gradient|| + 1) or when the gradient stops decreasing."""
+    y = np.asarray(y, dtype=np.float64)
+    n = y.size
+    a = y / (2.0 * lam) if alpha0 is None else np.array(alpha0, dtype=np.float64)
+    g = contract(a)
+    f = logistic_dual_objective(g, a, y, lam, m)
+    gr = logistic_dual_grad(g, a, y, lam)
+    best = (np.linalg.norm(gr), a.copy())
+    stall = 0
+    converged = False
+    it = 0
+    for it in range(1, max_iter + 1):
+        gn = np.linalg.norm(gr)
+        scale = np.linalg.norm(g) + np.linalg.norm(gr - g) + 1.0
+        if gn <= rtol * scale:
+            converged = True
+            it -= 1
+            break
+        H = jacobian(a) + np.diag(logistic_dual_hess_diag(a, y, lam))
+        step = -sla.cho_solve(sla.cho_factor(H, lower=True), gr)
+        # largest t keeping p + t dp inside (0, 1), dp = lam y step
+        p = lam * y * a
+        dp = lam * y * step
+        tmax = np.inf
+        neg, pos = dp < 0, dp > 0
+        if neg.any():
+            tmax = min(tmax, float(np.min(-p[neg] / dp[neg])))
+        if pos.any():
+            tmax = min(tmax, float(np.min((1 - p[pos]) / dp[pos])))
+        t = min(1.0, 0.99 * tmax)
+        slope = float(gr @ step)
+        while True:
+            a_new = a + t * step
+            g_new = contract(a_new)
+            f_new = logistic_dual_objective(g_new, a_new, y, lam, m)
+            if f_new <= f + 1e-4 * t * slope or t < 1e-14:
+                break
+            t *= 0.5
+        a, g, f = a_new, g_new, f_new
+        gr = logistic_dual_grad(g, a, y, lam)
+        gn_new = np.linalg.norm(gr)
+        if gn_new < best[0]:
+            best = (gn_new, a.copy())
+        if gn_new > 0.5 * gn and gn < 1e-8 * scale:
+            stall += 1
+            if stall >= 3:
+                converged = True
+                break
+        else:
+            stall = 0
+    gn, a = best
+    g = contract(a)
+    return a, SolveInfo(it, float(np.linalg.norm(logistic_dual_grad(g, a, y, lam))), converged,
+                        logistic_dual_objective(g, a, y, lam, m))
+
+
+def solve_logistic_linear(X, y, lam: float, m: int, **kw):
+    c, j = linear_callbacks(X, m)
+    return solve_dual_logistic(c, j, y, lam, m, **kw)
+
+
+def logistic_primal_objective(X, y, w, lam: float, m: int) -> float:
+    """F(w) = gamma sum_i L(y_i, <x_i, w>) + (1/p) ||w||_p^p (eq. tensor_infinite_2, gamma = 1/lam)."""
+    p = m / (m - 1.0)
+    return float(np.sum(logistic_loss(y, np.asarray(X) @ w))) / lam + float(np.sum(np.abs(w) ** p)) / p

@@ -36,6 +36,10 @@ class SolveOpts(ctypes.Structure):
         ("precond", c_int),
         ("precond_refresh", c_int),
         ("continuation", c_int),
+        ("loss", c_int),
+        ("support_stop", c_int),
+        ("support_X", c_vp),
+        ("support_d", c_i64),
     ]
 
 
@@ -50,6 +54,7 @@ class SolveInfo(ctypes.Structure):
         ("status", c_int),
         ("hess_passes", c_int),
         ("precond_updates", c_int),
+        ("stop_reason", c_int),
     ]
 
     def as_dict(self):
@@ -72,10 +77,19 @@ _SIGNATURES = {
                             ctypes.POINTER(c_int), ctypes.POINTER(c_dbl)]),
     "tk_solve_opts_default": (None, [ctypes.POINTER(SolveOpts)]),
     "tk_solve_workspace": (c_int, [c_i64, c_int, c_i64, c_int, ctypes.POINTER(c_sz)]),
+    "tk_solve_workspace_ex": (c_int, [c_i64, c_int, c_i64, c_int, c_i64, ctypes.POINTER(c_sz)]),
+    "tk_packed_stride": (c_int, [c_i64, c_int, c_int, ctypes.POINTER(c_i64)]),
+    "tk_build_packed_multi": (c_int, [c_vp, c_i64, c_i64, c_i64, c_int, c_int, c_dbl, c_int, c_vp, c_i64, c_vp]),
+    "tk_contract_multi": (c_int, [c_vp, c_int, c_i64, c_int, c_i64, c_i64, c_vp, c_vp, c_int, c_vp, c_sz, c_vp]),
+    "tk_solve_dual_multi": (c_int, [c_vp, c_int, c_i64, c_int, c_i64, c_i64, c_vp, ctypes.POINTER(c_dbl), c_i64,
+                                    ctypes.POINTER(SolveOpts), c_vp, ctypes.POINTER(SolveInfo), c_vp, c_sz, c_vp]),
     "tk_solve_dual": (c_int, [c_vp, c_int, c_i64, c_int, c_vp, ctypes.POINTER(c_dbl), c_i64,
                               ctypes.POINTER(SolveOpts), c_vp, ctypes.POINTER(SolveInfo), c_vp, c_sz, c_vp]),
     "tk_primal_weights": (c_int, [c_vp, c_i64, c_i64, c_int, c_vp, c_i64, c_vp, c_vp]),
     "tk_predict": (c_int, [c_vp, c_i64, c_i64, c_vp, c_i64, c_vp, c_vp]),
+    "tk_predict_kernel_workspace": (c_int, [c_i64, c_int, c_i64, c_i64, ctypes.POINTER(c_sz)]),
+    "tk_predict_kernel": (c_int, [c_vp, c_i64, c_i64, c_int, c_int, c_dbl, c_vp, c_i64, c_vp, c_i64, c_vp,
+                                  c_vp, c_sz, c_vp]),
     "tk_contract_dense": (c_int, [c_vp, c_i64, c_i64, c_int, c_vp, c_i64, c_vp, c_vp, c_vp]),
     "tk_support": (c_int, [c_vp, c_i64, c_i64, c_vp, c_vp, c_vp]),
     "tk_gather_rows": (c_int, [c_vp, c_i64, c_i64, c_vp, c_i64, c_vp, c_vp]),
@@ -83,6 +97,7 @@ _SIGNATURES = {
     "tk_dmse_dlambda": (c_int, [c_vp, c_int, c_i64, c_int, c_vp, c_i64, c_vp, c_dbl, c_vp, c_vp, c_i64,
                                 c_dbl, c_int, ctypes.POINTER(c_dbl), ctypes.POINTER(c_dbl), c_vp, c_vp,
                                 c_sz, c_vp]),
+    "tk_probe_stream_read": (c_int, [c_vp, c_i64, c_vp, c_int, c_vp]),
     "tk_timing_start": (c_int, []),
     "tk_timing_stop": (c_int, [ctypes.POINTER(c_i64), ctypes.POINTER(c_dbl), ctypes.POINTER(c_dbl)]),
 }

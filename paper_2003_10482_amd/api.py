@@ -181,18 +181,10 @@ def autotune(K: PackedTensor, alpha: torch.Tensor, v: Optional[torch.Tensor] = N
     return tile.value, {t: ms[i] for i, t in enumerate((1, 2, 4)) if ms[i] >= 0}, out
 
 
-def solve_dual(K: PackedTensor, y: torch.Tensor, lambdas: Sequence[float], tol: float = 1e-11,
-               max_newton: int = 100, max_cg: int = 2000, fixed_iters: int = 0,
-               alpha0: Optional[torch.Tensor] = None, polish: Optional[PackedTensor] = None,
-               verbose: bool = False, raise_on_noconv: bool = False, precond: bool = True,
-               precond_refresh: int = 25, continuation: bool = True):
-    """Dual solve for every lambda.  Returns (alpha [B, n], list of info dicts).
-    precond: Newton systems on the assembled Hessian with an inverse
-    preconditioner (else unpreconditioned CG on tensor passes); continuation: lambdas solved from the
-    largest down, each from the previous solution (else in lock step)."""
-    y = _dev_f64(y, "y")
-    lams = [float(x) for x in lambdas]
-    B = len(lams)
+LOSSES = {"square": 0, "logistic": 1}
+
+
+def _opts(tol, max_newton, max_cg, fixed_iters, verbose, precond, precond_refresh, continuation, loss):
     opts = _lib.SolveOpts()
     _lib.load().tk_solve_opts_default(ctypes.byref(opts))
     opts.tol = tol
@@ -203,7 +195,42 @@ def solve_dual(K: PackedTensor, y: torch.Tensor, lambdas: Sequence[float], tol: 
     opts.precond = int(precond)
     opts.precond_refresh = int(precond_refresh)
     opts.continuation = int(continuation)
+    opts.loss = LOSSES[loss] if isinstance(loss, str) else int(loss)
+    return opts
+
+
+def solve_dual(K: PackedTensor, y: torch.Tensor, lambdas: Sequence[float], tol: float = 1e-11,
+               max_newton: int = 100, max_cg: int = 2000, fixed_iters: int = 0,
+               alpha0: Optional[torch.Tensor] = None, polish: Optional[PackedTensor] = None,
+               verbose: bool = False, raise_on_noconv: bool = False, precond: bool = True,
+               precond_refresh: int = 25, continuation: bool = True, loss="square",
+               support_stop: int = 0, support_X: Optional[torch.Tensor] = None):
+    """Dual solve for every lambda.  Returns (alpha [B, n], list of info dicts).
+    precond: Newton systems on the assembled Hessian with an inverse
+    preconditioner (else unpreconditioned CG on tensor passes); continuation: lambdas solved from the
+    largest down, each from the previous solution (else in lock step).  loss: "square" or
+    "logistic" (labels in {-1, +1}).  support_stop > 0 (linear kernel, support_X = the points):
+    also stop once the 2-std support of w has not changed for that many Newton steps."""
+    y = _dev_f64(y, "y")
+    if y.numel() != K.n:
+        raise ValueError(f"y has {y.numel()} entries but the tensor has n = {K.n}")
+    lams = [float(x) for x in lambdas]
+    B = len(lams)
+    opts = _opts(tol, max_newton, max_cg, fixed_iters, verbose, precond, precond_refresh, continuation, loss)
+    sd = 0
+    if support_stop > 0:
+        if support_X is None:
+            raise ValueError("support_stop needs support_X (the points the tensor was built from)")
+        support_X = _dev_f64(support_X, "support_X")
+        if support_X.shape[0] != K.n:
+            raise ValueError("support_X must have n rows")
+        sd = support_X.shape[1]
+        opts.support_stop = int(support_stop)
+        opts.support_X = support_X.data_ptr()
+        opts.support_d = sd
     if polish is not None:
+        if polish.n != K.n or polish.m != K.m or polish.dtype != F64:
+            raise ValueError("the polish tensor must be an FP64 tensor of the same n and m")
         opts.polish_K = polish.data.data_ptr()
         opts.polish_dtype = polish.dtype
     alpha = torch.zeros(B, K.n, dtype=torch.float64, device=y.device)
@@ -212,12 +239,74 @@ def solve_dual(K: PackedTensor, y: torch.Tensor, lambdas: Sequence[float], tol: 
         opts.warm_start = 1
     infos = (_lib.SolveInfo * B)()
     h_l = (ctypes.c_double * B)(*lams)
-    work = _workspace(solve_workspace(K.n, K.m, B, K.dtype), y.device)
+    ws = ctypes.c_size_t()
+    _lib.check(_lib.load().tk_solve_workspace_ex(K.n, K.m, B, K.dtype, sd, ctypes.byref(ws)))
+    work = _workspace(ws.value, y.device)
     rc = _lib.load().tk_solve_dual(_ptr(K.data), K.dtype, K.n, K.m, _ptr(y), h_l, B, ctypes.byref(opts),
                                    _ptr(alpha), infos, _ptr(work), work.numel(), _stream())
     if rc != 0 and (raise_on_noconv or rc not in (-5, -6)):
         _lib.check(rc)
     return alpha, [infos[i].as_dict() for i in range(B)]
+
+
+class MultiPackedTensor:
+    """T packed tensors of the same (n, m, dtype), tensor t at t * stride entries."""
+
+    def __init__(self, data: torch.Tensor, T: int, n: int, m: int, dtype: int, stride: int):
+        self.data, self.T, self.n, self.m, self.dtype, self.stride = data, T, n, m, dtype, stride
+
+    def tensor(self, t: int) -> PackedTensor:
+        return PackedTensor(self.data[t * self.stride: t * self.stride + packed_count(self.n, self.m)],
+                            self.n, self.m, self.dtype)
+
+
+def packed_stride(n: int, m: int, dtype) -> int:
+    out = ctypes.c_int64()
+    _lib.check(_lib.load().tk_packed_stride(n, m, _DTYPES[dtype], ctypes.byref(out)))
+    return out.value
+
+
+def build_packed_multi(Xs: torch.Tensor, m: int, kernel="linear", kparam: float = 0.0,
+                       dtype="f64") -> MultiPackedTensor:
+    """Xs [T, n, d]: one packed tensor per draw, side by side."""
+    Xs = _dev_f64(Xs, "Xs")
+    T, n, d = Xs.shape
+    dt = _DTYPES[dtype]
+    stride = packed_stride(n, m, dt)
+    data = torch.zeros(T * stride, dtype=_TORCH_STORAGE[dt], device=Xs.device)
+    _lib.check(_lib.load().tk_build_packed_multi(_ptr(Xs), T, n, d, m, _KERNELS[kernel], float(kparam), dt,
+                                                 _ptr(data), stride, _stream()))
+    return MultiPackedTensor(data, T, n, m, dt, stride)
+
+
+def contract_multi(Km: MultiPackedTensor, alpha: torch.Tensor, acc: int = ACC_AUTO) -> torch.Tensor:
+    """g_t = K_t . alpha_t^{m-1}, alpha [T, n] -> [T, n], one launch per pass."""
+    alpha = _dev_f64(alpha, "alpha").reshape(Km.T, Km.n)
+    g = torch.empty_like(alpha)
+    work = _workspace(contract_workspace(Km.n, Km.m, Km.T, Km.dtype), alpha.device)
+    _lib.check(_lib.load().tk_contract_multi(_ptr(Km.data), Km.dtype, Km.n, Km.m, Km.T, Km.stride, _ptr(alpha),
+                                             _ptr(g), acc, _ptr(work), work.numel(), _stream()))
+    return g
+
+
+def solve_dual_multi(Km: MultiPackedTensor, Y: torch.Tensor, lambdas: Sequence[float], tol: float = 1e-11,
+                     max_newton: int = 100, max_cg: int = 2000, loss="square", verbose: bool = False):
+    """Every (draw, lambda) dual: Y [T, n] responses; returns (alpha [L, T, n],
+    infos [L][T]).  Draws in lock step, lambdas by continuation."""
+    Y = _dev_f64(Y, "Y").reshape(Km.T, Km.n)
+    lams = [float(x) for x in lambdas]
+    L = len(lams)
+    opts = _opts(tol, max_newton, max_cg, 0, verbose, True, 25, True, loss)
+    alpha = torch.zeros(L, Km.T, Km.n, dtype=torch.float64, device=Y.device)
+    infos = (_lib.SolveInfo * (L * Km.T))()
+    h_l = (ctypes.c_double * L)(*lams)
+    work = _workspace(solve_workspace(Km.n, Km.m, min(Km.T, 64), Km.dtype), Y.device)
+    rc = _lib.load().tk_solve_dual_multi(_ptr(Km.data), Km.dtype, Km.n, Km.m, Km.T, Km.stride, _ptr(Y), h_l, L,
+                                         ctypes.byref(opts), _ptr(alpha), infos, _ptr(work), work.numel(),
+                                         _stream())
+    if rc != 0 and rc not in (-5, -6):
+        _lib.check(rc)
+    return alpha, [[infos[l * Km.T + t].as_dict() for t in range(Km.T)] for l in range(L)]
 
 
 def primal_weights(X: torch.Tensor, alpha: torch.Tensor, m: int) -> torch.Tensor:
@@ -238,6 +327,26 @@ def predict(W: torch.Tensor, Xq: torch.Tensor) -> torch.Tensor:
     f = torch.empty(W2.shape[0], N, dtype=torch.float64, device=W.device)
     _lib.check(_lib.load().tk_predict(_ptr(W2), d, W2.shape[0], _ptr(Xq), N, _ptr(f), _stream()))
     return f if W.dim() == 2 else f[0]
+
+
+def predict_kernel(X: torch.Tensor, alpha: torch.Tensor, Xq: torch.Tensor, m: int, kernel="linear",
+                   kparam: float = 0.0) -> torch.Tensor:
+    """General tensor-kernel prediction: f_b(x) = sum over sorted (m-1)-tuples T
+    of c(T) alpha_b^T k(x_T, x).  alpha [n] or [B, n] -> f [N] or [B, N]."""
+    X, alpha, Xq = _dev_f64(X, "X"), _dev_f64(alpha, "alpha"), _dev_f64(Xq, "Xq")
+    n, d = X.shape
+    N, dq = Xq.shape
+    if dq != d:
+        raise ValueError("X and Xq have different feature counts")
+    a2 = alpha.reshape(-1, n)
+    B = a2.shape[0]
+    f = torch.empty(B, N, dtype=torch.float64, device=X.device)
+    ws = ctypes.c_size_t()
+    _lib.check(_lib.load().tk_predict_kernel_workspace(n, m, B, N, ctypes.byref(ws)))
+    work = _workspace(ws.value, X.device)
+    _lib.check(_lib.load().tk_predict_kernel(_ptr(X), n, d, m, _KERNELS[kernel], float(kparam), _ptr(a2), B,
+                                             _ptr(Xq), N, _ptr(f), _ptr(work), work.numel(), _stream()))
+    return f if alpha.dim() == 2 else f[0]
 
 
 def contract_dense(X: torch.Tensor, alpha: torch.Tensor, m: int) -> torch.Tensor:
@@ -280,6 +389,10 @@ def dmse_dlambda(K: PackedTensor, X: torch.Tensor, alpha: torch.Tensor, lam: flo
     X, alpha = _dev_f64(X, "X"), _dev_f64(alpha, "alpha")
     X_val, y_val = _dev_f64(X_val, "X_val"), _dev_f64(y_val, "y_val")
     n, d = X.shape
+    if n != K.n:
+        raise ValueError(f"X has {n} rows but the tensor has n = {K.n}")
+    if alpha.numel() != n or X_val.shape[1] != d or y_val.numel() != X_val.shape[0]:
+        raise ValueError("alpha, X_val or y_val shape does not match X")
     nval = X_val.shape[0]
     ws = ctypes.c_size_t()
     _lib.check(_lib.load().tk_dmse_workspace(n, K.m, d, nval, K.dtype, ctypes.byref(ws)))
@@ -332,3 +445,18 @@ def timing_stop() -> dict:
     by = (ctypes.c_double * k)()
     _lib.check(_lib.load().tk_timing_stop(n, ms, by))
     return {name: (n[i], ms[i], by[i]) for i, name in enumerate(TIMING_KINDS)}
+
+
+def probe_stream_read(buf: torch.Tensor, groups: int = 2048,
+                      sink: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Instrumentation: stream the bytes of a device buffer (its size rounded
+    down to 16 bytes) through a plain read kernel; returns the per-workgroup
+    checksums.  Timed with events, it gives the device's achievable HBM read
+    rate."""
+    if not buf.is_cuda:
+        raise ValueError("buf must be a device tensor")
+    nbytes = (buf.numel() * buf.element_size()) // 16 * 16
+    if sink is None:
+        sink = torch.empty(groups, dtype=torch.int64, device=buf.device)
+    _lib.check(_lib.load().tk_probe_stream_read(_ptr(buf), nbytes, _ptr(sink), groups, _stream()))
+    return sink

@@ -17,7 +17,7 @@ OUT = os.path.join(HERE, "libtk.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 ARCH = os.environ.get("TK_OFFLOAD_ARCH", "gfx950")
 SOURCES = ["tk_pass_dd.hip", "tk_pass_f64.hip", "tk_pass_f32.hip", "tk_contract.hip", "tk_build.hip",
-           "tk_dense.hip", "tk_vec.hip", "tk_hess.hip", "tk_abi.hip"]
+           "tk_dense.hip", "tk_predict.hip", "tk_vec.hip", "tk_hess.hip", "tk_abi.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result", "-munsafe-fp-atomics", "-ffp-contract=off"]
@@ -30,8 +30,23 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src: str) -> str:
+def _up_to_date(src: str, obj: str) -> bool:
+    """The object is newer than its source and than every header of csrc/ and
+    include/ (a coarse rule: any header change rebuilds everything)."""
+    if not os.path.exists(obj):
+        return False
+    t = os.path.getmtime(obj)
+    deps = [os.path.join(CSRC, src)]
+    deps += [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".hpp")]
+    inc = os.path.join(os.path.dirname(HERE), "include")
+    deps += [os.path.join(inc, h) for h in os.listdir(inc) if h.endswith(".h")]
+    return all(os.path.getmtime(p) < t for p in deps)
+
+
+def _compile(src: str, changed_only: bool = False) -> str:
     obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
+    if changed_only and _up_to_date(src, obj):
+        return obj
     cmd = [hipcc(), *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
@@ -39,11 +54,13 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, changed_only: bool = False) -> str:
+    """Compile every source (changed_only: only those whose object is older
+    than the source or a header) and link libtk.so."""
     os.makedirs(BUILD_DIR, exist_ok=True)
     jobs = min(len(SOURCES), max(1, (os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, changed_only), SOURCES))
     tmp = OUT + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -56,4 +73,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, changed_only="--changed" in sys.argv[1:])

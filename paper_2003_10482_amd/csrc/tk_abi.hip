@@ -189,20 +189,42 @@ void timing_end(TimedLaunch &tl, hipStream_t st)
 
 namespace {
 
+// Device memory that receives the work plans of the passes (instead of the
+// library's cached device plans, which are allocated on first use of a
+// shape), for callers that cannot allocate.  Timing instrumentation is off
+// on that route (it creates events).
+struct PlanArea {
+    unsigned char *dev;
+    size_t bytes;
+};
+
+size_t plan_area_bytes(const ContractPlan &pl)
+{
+    size_t b = 0;
+    for (int i = 0; i < pl.npass; ++i) b += align256(((size_t)pl.pass[i].groups * 4 + 1) * sizeof(int64_t));
+    return b;
+}
+
 // Run every pass of the contraction (and its tangent when vdir != null).
 int run_contract(const void *K, int dtype, int64_t n, int m, const double *alpha, const double *vdir,
                  int64_t B, double *g, double *h, int mode, void *work, size_t work_bytes, hipStream_t st,
-                 int force_bt = 0)
+                 int force_bt = 0, const PlanArea *area = nullptr, int64_t k_stride = 0)
 {
     const bool hv = vdir != nullptr;
+    // several tensors (vector b contracts tensor b, k_stride entries apart):
+    // one vector per tile
+    if (k_stride > 0) force_bt = 1;
     const ContractPlan pl = make_plan(n, m, B, mode, hv, dtype, force_bt);
     if (work_bytes < pl.bytes || (pl.bytes && !work))
         return fail(TK_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", work_bytes, pl.bytes);
+    if (area && plan_area_bytes(pl) > area->bytes)
+        return fail(TK_ENOMEM, "work plans need %zu bytes of the %zu reserved", plan_area_bytes(pl), area->bytes);
+    size_t area_off = 0;
     unsigned char *w = reinterpret_cast<unsigned char *>(work);
     const void *A = K;
     const void *Ad = nullptr;
     int in_kind = pass_in_kind(0, dtype, mode);
-    int64_t a_stride = 0;
+    int64_t a_stride = k_stride;
     double mu = 1.0;
     ReduceParams rv{}, rt{};
     for (int i = 0; i < pl.npass; ++i) {
@@ -223,12 +245,21 @@ int run_contract(const void *K, int dtype, int64_t n, int m, const double *alpha
         prm.part = reinterpret_cast<double *>(w + pp.p_off);
         prm.part_d = hv ? reinterpret_cast<double *>(w + pp.p_off + pp.p_bytes) : nullptr;
         int perr = 0;
-        prm.plan = pass_plan(pp.q, n, pp.groups, &perr);
+        if (area) {
+            // the host plan lives for the process, so the copy may complete later
+            const std::vector<int64_t> &hp = pass_plan_host(pp.q, n, pp.groups);
+            int64_t *dp = reinterpret_cast<int64_t *>(area->dev + area_off);
+            area_off += align256(hp.size() * sizeof(int64_t));
+            TK_HIP_CHECK(hipMemcpyAsync(dp, hp.data(), hp.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+            prm.plan = dp;
+        } else {
+            prm.plan = pass_plan(pp.q, n, pp.groups, &perr);
+        }
         if (perr || !prm.plan) return fail(TK_EHIP, "could not place the work plan of pass q=%d", pp.q);
         const int hvl = pass_hv(i, hv);
         const int bt = pp.bt;
         TimedLaunch tl{};
-        if (i == 0)   // one read of the stored tensor per tile of bt vectors
+        if (i == 0 && !area)   // one read of the stored tensor(s) per tile of bt vectors
             tl = timing_begin(hv ? 1 : (mode == ACC_DD ? 0 : 2),
                               (double)pp.count * (double)dtype_size(dtype) * (double)((B + bt - 1) / bt), st);
         hipError_t e = launch_pass(pp.q, in_kind, mode, hvl, bt, prm, pp.groups, st);
@@ -455,6 +486,17 @@ int tk_autotune(const void *d_K, int dtype, int64_t n, int m, const double *d_al
     return rc;
 }
 
+int tk_probe_stream_read(const void *d_src, int64_t bytes, uint64_t *d_sink, int groups, void *stream)
+{
+    if (!d_src || !d_sink) return fail(TK_EINVAL, "null device pointer");
+    if (bytes < 16 || (bytes & 15)) return fail(TK_EINVAL, "bytes must be a positive multiple of 16");
+    if (reinterpret_cast<uintptr_t>(d_src) & 15) return fail(TK_EINVAL, "d_src must be 16-byte aligned");
+    if (groups < 1 || groups > 65536) return fail(TK_EINVAL, "groups must be in [1, 65536]");
+    hipError_t e = probe_stream_read(d_src, bytes / 16, d_sink, groups, as_stream(stream));
+    if (e != hipSuccess) return fail(TK_EHIP, "stream read failed: %s", hipGetErrorString(e));
+    return TK_OK;
+}
+
 int tk_timing_start(void)
 {
     std::lock_guard<std::mutex> lk(g_timing_mu);
@@ -512,33 +554,63 @@ namespace tk {
 namespace {
 
 struct SolveBuffers {
-    double *g, *grad, *x, *r, *dv, *hd, *at, *gt, *z, *best, *stats, *stats2;
+    double *g, *grad, *x, *r, *dv, *hd, *at, *gt, *z, *best, *hdiag, *stats, *stats2;
     double *P;             // [B][n][n] preconditioners (inverse Hessians)
     double *Jd;            // [B][n][n] Hessians J at the current iterates
     unsigned char *hw;     // Hessian kernel workspace
     size_t hw_bytes;
+    double *supW;          // [B][d] primal weights for the support test (early stopping)
+    uint8_t *mask_cur, *mask_prev;   // [B][d] current and previous supports
+    double *sup_tau;       // [B] thresholds
+    int *sup_cnt;          // [B] changed entries since the last Newton step
     unsigned char *cw;
     size_t cw_bytes;
 };
 
-size_t solve_ws(int64_t n, int m, int64_t B, int dtype)
+// Extensions of one batch of dual solves beyond the square loss on a shared
+// tensor: several tensors (problem b on the tensor k_stride entries after
+// problem b-1's) with their own responses, the logistic loss, and the
+// stable-support stopping rule.
+struct SolveCtx {
+    int64_t k_stride = 0;   // entries between the problems' tensors (0: one tensor)
+    int64_t y_stride = 0;   // entries between the problems' responses (0: one response)
+    int loss = TK_LOSS_SQUARE;
+    int support_stop = 0;   // Newton steps in a row with an unchanged support that end a solve
+    const double *sX = nullptr;   // points of the linear tensor kernel [n][d] (support test)
+    int64_t sd = 0;
+};
+
+size_t support_ws(int64_t B, int64_t d)
 {
-    const size_t vec = align256((size_t)B * n * sizeof(double));
-    size_t cw = contract_ws(n, m, B, dtype);
-    const size_t cw64 = contract_ws(n, m, B, TK_F64);   // polish passes on an FP64 tensor
-    if (cw64 > cw) cw = cw64;
-    return 10 * vec + 2 * align256((size_t)B * 8 * sizeof(double)) + align256((size_t)B * n * n * sizeof(double)) +
-           align256((size_t)B * n * n * sizeof(double)) + align256(hessian_ws(n, m)) + cw;
+    if (d <= 0) return 0;
+    return align256((size_t)B * d * sizeof(double)) + 2 * align256((size_t)B * d) + align256((size_t)B * 8) +
+           align256((size_t)B * sizeof(int));
 }
 
-SolveBuffers carve(void *work, int64_t n, int m, int64_t B, size_t total)
+size_t solve_ws(int64_t n, int m, int64_t B, int dtype, int64_t support_d = 0)
+{
+    const size_t vec = align256((size_t)B * n * sizeof(double));
+    // passes for the whole batch (lock step) or one problem at a time
+    // (continuation): a single vector's launch has more workgroups, so its
+    // partials can outgrow a batch's
+    size_t cw = 0;
+    for (int64_t bb : {B, (int64_t)1})
+        for (int dt : {dtype, (int)TK_F64}) {   // polish passes run on an FP64 tensor
+            const size_t c = contract_ws(n, m, bb, dt);
+            if (c > cw) cw = c;
+        }
+    return 11 * vec + 2 * align256((size_t)B * 8 * sizeof(double)) + align256((size_t)B * n * n * sizeof(double)) +
+           align256((size_t)B * n * n * sizeof(double)) + align256(hessian_ws(n, m)) + support_ws(B, support_d) + cw;
+}
+
+SolveBuffers carve(void *work, int64_t n, int m, int64_t B, size_t total, int64_t support_d = 0)
 {
     SolveBuffers s{};
     const size_t vec = align256((size_t)B * n * sizeof(double));
     unsigned char *w = reinterpret_cast<unsigned char *>(work);
-    double **v[10] = {&s.g, &s.grad, &s.x, &s.r, &s.dv, &s.hd, &s.at, &s.gt, &s.z, &s.best};
-    for (int i = 0; i < 10; ++i) *v[i] = reinterpret_cast<double *>(w + i * vec);
-    size_t used = 10 * vec;
+    double **v[11] = {&s.g, &s.grad, &s.x, &s.r, &s.dv, &s.hd, &s.at, &s.gt, &s.z, &s.best, &s.hdiag};
+    for (int i = 0; i < 11; ++i) *v[i] = reinterpret_cast<double *>(w + i * vec);
+    size_t used = 11 * vec;
     s.stats = reinterpret_cast<double *>(w + used);
     used += align256((size_t)B * 8 * sizeof(double));
     s.stats2 = reinterpret_cast<double *>(w + used);
@@ -550,6 +622,19 @@ SolveBuffers carve(void *work, int64_t n, int m, int64_t B, size_t total)
     s.hw = w + used;
     s.hw_bytes = align256(hessian_ws(n, m));
     used += s.hw_bytes;
+    if (support_d > 0) {
+        const int64_t d = support_d;
+        s.supW = reinterpret_cast<double *>(w + used);
+        used += align256((size_t)B * d * sizeof(double));
+        s.mask_cur = w + used;
+        used += align256((size_t)B * d);
+        s.mask_prev = w + used;
+        used += align256((size_t)B * d);
+        s.sup_tau = reinterpret_cast<double *>(w + used);
+        used += align256((size_t)B * 8);
+        s.sup_cnt = reinterpret_cast<int *>(w + used);
+        used += align256((size_t)B * sizeof(int));
+    }
     s.cw = w + used;
     s.cw_bytes = total - used;
     return s;
@@ -674,8 +759,20 @@ struct ProblemState {
 // directional-derivative passes over the tensor instead.
 int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, const double *lams, int64_t B,
                 const tk_solve_opts &o, double *alpha, tk_solve_info *info, SolveBuffers &sb, hipStream_t st,
-                std::vector<Precond> &pc)
+                std::vector<Precond> &pc, const SolveCtx &cx)
 {
+    const bool logistic = cx.loss == TK_LOSS_LOGISTIC;
+    // D from the statistics [a.g, a.a, y.a or S, grad.grad] of one problem
+    auto dual_of = [&](const double *st4, double lam_b) {
+        return logistic ? st4[0] / m + st4[2] / lam_b : st4[0] / m + 0.5 * lam_b * st4[1] - st4[2];
+    };
+    // tensor of problem b (and of its polish)
+    auto kptr = [&](const void *Kb, int dt, int64_t b) -> const void * {
+        return reinterpret_cast<const unsigned char *>(Kb) + (size_t)b * (size_t)cx.k_stride * dtype_size(dt);
+    };
+    std::vector<int> stable(B, 0);
+    // why a problem stopped: TK_STOP_TOL, TK_STOP_SUPPORT, TK_STOP_FLOOR
+    std::vector<int> reason(B, TK_STOP_TOL);
     std::vector<ProblemState> ps(B);
     for (int64_t b = 0; b < B; ++b) {
         ps[b] = ProblemState{};
@@ -690,7 +787,6 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
     int passes = 0, hess_passes = 0;
     std::vector<int> pc_updates(B, 0);
     std::vector<double> hst(B * 4), hd(B), hr(B);
-    const double inv_m = 1.0 / m;
     const bool use_pc = o.precond != 0 && n <= 256;
     const int refresh = o.precond_refresh > 0 ? o.precond_refresh : 8;
 
@@ -710,19 +806,25 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
     bool accurate = true;
     double ynorm = 0.0;
     {
-        TK_HIP_CHECK(vec_dot(y, y, 0, sb.stats, 1, n, st));
-        TK_HIP_CHECK(hipMemcpyAsync(&ynorm, sb.stats, sizeof(double), hipMemcpyDeviceToHost, st));
+        const int64_t rows = cx.y_stride > 0 ? B : 1;   // per-problem responses (y_stride = n) or one
+        std::vector<double> yy(rows);
+        TK_HIP_CHECK(vec_dot(y, y, cx.y_stride, sb.stats, rows, n, st));
+        TK_HIP_CHECK(hipMemcpyAsync(yy.data(), sb.stats, rows * sizeof(double), hipMemcpyDeviceToHost, st));
         TK_HIP_CHECK(hipStreamSynchronize(st));
-        ynorm = std::sqrt(ynorm);
+        for (double v : yy) ynorm = std::max(ynorm, std::sqrt(v));
     }
     // gradient pass at `a` into (gdst, graddst), statistics to the host
     auto gradient = [&](const void *Kp, int dt, const double *a, double *gdst, double *graddst,
                         std::vector<double> &out) -> int {
         int mode = dt == TK_F64 ? (accurate ? ACC_DD : ACC_PLAIN64) : ACC_PLAIN32;
-        int rc = run_contract(Kp, dt, n, m, a, nullptr, B, gdst, nullptr, mode, sb.cw, sb.cw_bytes, st);
+        int rc = run_contract(Kp, dt, n, m, a, nullptr, B, gdst, nullptr, mode, sb.cw, sb.cw_bytes, st, 0, nullptr,
+                              cx.k_stride);
         if (rc) return rc;
         passes++;
-        TK_HIP_CHECK(vec_grad(gdst, a, y, lam, graddst, sb.stats, B, n, st));
+        if (logistic)
+            TK_HIP_CHECK(vec_grad_logistic(gdst, a, y, cx.y_stride, lam, graddst, sb.hdiag, sb.stats, B, n, st));
+        else
+            TK_HIP_CHECK(vec_grad(gdst, a, y, lam, graddst, sb.stats, B, n, st, cx.y_stride));
         return sync_copy(out.data(), sb.stats, B * 4);
     };
 
@@ -741,21 +843,28 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
         const void *Kh = (dt != TK_F64 && o.polish_K) ? o.polish_K : Kp;
         const int dth = (dt != TK_F64 && o.polish_K) ? TK_F64 : dt;
         int hp = 0;
-        int rc = run_hessian(Kh, dth, n, m, alpha + b * n, Jb, sb.hw, sb.hw_bytes, st, &hp);
+        int rc = run_hessian(kptr(Kh, dth, b), dth, n, m, alpha + b * n, Jb, sb.hw, sb.hw_bytes, st, &hp);
         if (rc) return rc;
         hess_passes += hp;
         return TK_OK;
     };
-    // (J_b + lambda I)^{-1} into the device preconditioner slot b, factored on
-    // the host (Cholesky); a rounded J may miss positive definiteness by its
-    // rounding: shift more.  J = 0 gives I / lambda directly.
+    // (J_b + lambda I)^{-1} (J_b + diag(h_b) for the logistic loss) into the
+    // device preconditioner slot b, factored on the host (Cholesky); a rounded
+    // J may miss positive definiteness by its rounding: shift more.  J = 0
+    // gives I / lambda directly.
     auto refresh_inverse = [&](int64_t b, bool zero) -> int {
         std::vector<double> A((size_t)n * n, 0.0);
+        std::vector<double> hdg;
         if (zero) {
             for (int64_t i = 0; i < n; ++i) A[i * n + i] = 1.0 / ps[b].lam;
         } else {
             TK_HIP_CHECK(hipMemcpyAsync(A.data(), sb.Jd + b * n * n, (size_t)n * n * sizeof(double),
                                         hipMemcpyDeviceToHost, st));
+            if (logistic) {
+                hdg.resize(n);
+                TK_HIP_CHECK(hipMemcpyAsync(hdg.data(), sb.hdiag + b * n, n * sizeof(double), hipMemcpyDeviceToHost,
+                                            st));
+            }
             TK_HIP_CHECK(hipStreamSynchronize(st));
             double tr = 0.0, fro = 0.0;
             for (int64_t i = 0; i < n; ++i) tr += std::fabs(A[i * n + i]);
@@ -765,7 +874,7 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
             bool ok = false;
             for (int attempt = 0; attempt < 40 && !ok; ++attempt) {
                 std::vector<double> T = A;
-                for (int64_t i = 0; i < n; ++i) T[i * n + i] += shift;
+                for (int64_t i = 0; i < n; ++i) T[i * n + i] += shift + (logistic ? hdg[i] - ps[b].lam : 0.0);
                 if (spd_inverse(T, (int)n)) {
                     A.swap(T);
                     ok = true;
@@ -791,6 +900,10 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
             for (int64_t b = 0; b < B; ++b) pc[b].have_J = false;
         const void *Kp = phase == 0 ? K : o.polish_K;
         const int dt = phase == 0 ? dtype : TK_F64;
+        // a phase on reduced storage: its gradients carry the storage rounding,
+        // so it keeps its iterate of smallest gradient and ends at the noise
+        // floor that rounding sets (handing over to the polish when there is one)
+        const bool reduced = dt != TK_F64;
         const int hv_mode = dt == TK_F64 ? ACC_PLAIN64 : ACC_PLAIN32;
         // reduced-precision phase followed by a polish: stop the first phase at a looser tolerance
         const double tol = (phases == 2 && phase == 0) ? std::max(o.tol, 1e-6) : o.tol;
@@ -807,7 +920,7 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                 s.ya = hst[4 * b + 2];
                 s.gn = std::sqrt(hst[4 * b + 3]);
                 s.an = std::sqrt(s.aa);
-                s.D = inv_m * s.ag + 0.5 * s.lam * s.aa - s.ya;
+                s.D = dual_of(&hst[4 * b], s.lam);
             }
         };
         if ((rc = gradient(Kp, dt, alpha, sb.g, sb.grad, hst))) return rc;
@@ -822,8 +935,8 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
         for (int64_t b = 0; b < B; ++b) gn0[b] = ps[b].gn > 0 ? ps[b].gn : 1.0;
         // reduced-precision phase before a polish: hand over once the gradient
         // stops shrinking (the rounded tensor's noise floor)
-        std::vector<double> best_gn(B, INFINITY);
-        std::vector<int> stalled(B, 0);
+        std::vector<double> best_gn(B, INFINITY), prev_Dr(B, INFINITY);
+        std::vector<int> stalled(B, 0), loose(B, 0);
         // ... and keep its iterate of smallest gradient: at small lambda the
         // rounded tensor's quartic form is not convex (its rounding reaches the
         // null space of X^T), Newton steps can run off along it, and the polish
@@ -852,32 +965,74 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                     take_stats();
                 }
             }
+            // stable-support stopping (Section 6.3 threshold): the support of
+            // w = (X^T alpha)^{m-1} compared with the last Newton step's
+            if (cx.support_stop > 0 && phase == phases - 1) {
+                TK_HIP_CHECK(launch_gemm(alpha, n, cx.sX, cx.sd, 1, sb.supW, cx.sd, B, cx.sd, n, m - 1, st));
+                TK_HIP_CHECK(launch_support(sb.supW, cx.sd, B, sb.mask_cur, sb.sup_tau, st));
+                TK_HIP_CHECK(vec_mask_diff(sb.mask_cur, sb.mask_prev, B, cx.sd, sb.sup_cnt, st));
+                std::vector<int> cnt(B);
+                TK_HIP_CHECK(hipMemcpyAsync(cnt.data(), sb.sup_cnt, B * sizeof(int), hipMemcpyDeviceToHost, st));
+                TK_HIP_CHECK(hipStreamSynchronize(st));
+                for (int64_t b = 0; b < B; ++b) {
+                    if (ps[b].done) continue;
+                    stable[b] = (it > 0 && cnt[b] == 0) ? stable[b] + 1 : 0;
+                    if (stable[b] >= cx.support_stop) {
+                        ps[b].done = true;
+                        reason[b] = TK_STOP_SUPPORT;
+                    }
+                }
+            }
             bool any = false;
             for (int64_t b = 0; b < B; ++b) {
                 ProblemState &s = ps[b];
                 if (!std::isfinite(s.gn) || !std::isfinite(s.D)) {
                     s.done = true;
                     s.status = TK_ENAN;
+                    reason[b] = TK_STOP_TOL;
                 }
-                if (!s.done && phases == 2 && phase == 0) {
+                if (!s.done && reduced) {
                     if (s.gn < kept_gn[b]) {
                         kept_gn[b] = s.gn;
                         TK_HIP_CHECK(hipMemcpyAsync(sb.best + b * n, alpha + b * n, n * sizeof(double),
                                                     hipMemcpyDeviceToDevice, st));
                     } else if (!(s.gn <= 1e3 * kept_gn[b])) {
                         s.done = true;   // running off on the rounded tensor
+                        reason[b] = TK_STOP_FLOOR;
                     }
                 }
                 // an exactly zero gradient is the optimum (y = 0 gives alpha = 0)
                 if (!s.done && o.fixed_iters <= 0 && (s.gn == 0 || (s.gn <= tol * s.lam * s.an && s.an > 0)))
                     s.done = true;
-                if (!s.done && phases == 2 && phase == 0) {
+                // the floor: Newton steps that no longer halve the gradient,
+                // three in a row, counted where the step was a full one (the
+                // local regime, where the exact problem's gradient would fall
+                // quadratically) or left D flat (below 1e-8 of it); damped
+                // steps that still decrease D (after a cold or warm start) do
+                // not count.  Twelve non-halving steps in a row end it anyway
+                // (at small lambda the rounded tensor's Hessian can be
+                // indefinite, and steepest-descent steps then crawl).  The
+                // iterate of smallest gradient is the one returned.
+                if (!s.done && reduced) {
+                    const bool flat = !(prev_Dr[b] - s.D > 1e-8 * std::fabs(s.D));
                     if (s.gn < 0.5 * best_gn[b]) {
                         best_gn[b] = s.gn;
                         stalled[b] = 0;
-                    } else if (++stalled[b] >= 3) {
-                        s.done = true;
+                        loose[b] = 0;
+                    } else {
+                        // a step without positive curvature (CG took no step: the
+                        // rounded tensor's Hessian is indefinite there) counts too
+                        // (with a polish tensor to hand over to, any non-halving
+                        // step counts: a late hand-over costs more than an early one)
+                        if (phases == 2 || std::fabs(last_t[b] - 1.0) <= 0.1 || flat ||
+                            (it > 0 && ps[b].last_cg == 0))
+                            ++stalled[b];
+                        if (stalled[b] >= 3 || ++loose[b] >= 12) {
+                            s.done = true;
+                            reason[b] = TK_STOP_FLOOR;
+                        }
                     }
+                    prev_Dr[b] = s.D;
                 }
                 any |= !s.done;
             }
@@ -903,7 +1058,10 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                         pc[b].moved = 0.0;
                         jfresh[b] = true;
                     }
-                    if (!pc[b].dev || (pc[b].ident && !zero) || ps[b].last_cg > refresh)
+                    // the logistic loss's separable Hessian lambda / (p (1-p)) changes
+                    // fast as iterates near the domain's boundary: a stale inverse
+                    // then steers CG into the step cap, so it is refreshed every step
+                    if (!pc[b].dev || (pc[b].ident && !zero) || ps[b].last_cg > refresh || logistic)
                         if ((rc = refresh_inverse(b, zero))) return rc;
                 }
             }
@@ -921,7 +1079,8 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                 Coefs etac{};
                 for (int64_t b = 0; b < B; ++b) etac.c[b] = eta[b];
                 int *dsteps = reinterpret_cast<int *>(sb.stats2);
-                TK_HIP_CHECK(vec_cg_dense(sb.Jd, sb.P, sb.grad, lam, etac, act, B, n, max_cg, sb.x, dsteps, st));
+                TK_HIP_CHECK(vec_cg_dense(sb.Jd, sb.P, sb.grad, lam, etac, act, B, n, max_cg, sb.x, dsteps, st,
+                                          logistic ? sb.hdiag : nullptr));
                 TK_HIP_CHECK(hipMemcpyAsync(cg_steps.data(), dsteps, B * sizeof(int), hipMemcpyDeviceToHost, st));
                 TK_HIP_CHECK(hipStreamSynchronize(st));
                 for (int64_t b = 0; b < B; ++b)
@@ -942,10 +1101,10 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                     for (int64_t b = 0; b < B; ++b) anycg |= cg_on[b];
                     if (!anycg) break;
                     if ((rc = run_contract(Kp, dt, n, m, alpha, sb.dv, B, nullptr, sb.hd, hv_mode, sb.cw, sb.cw_bytes,
-                                           st)))
+                                           st, 0, nullptr, cx.k_stride)))
                         return rc;
                     passes++;
-                    TK_HIP_CHECK(vec_shift_dot(sb.dv, sb.hd, lam, sb.stats, B, n, st));
+                    TK_HIP_CHECK(vec_shift_dot(sb.dv, sb.hd, lam, sb.stats, B, n, st, logistic ? sb.hdiag : nullptr));
                     if ((rc = sync_copy(hd.data(), sb.stats, B))) return rc;
                     Coefs a{};
                     for (int64_t b = 0; b < B; ++b) {
@@ -1005,7 +1164,15 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
             // so one directional-derivative pass at x along alpha (which also
             // returns K x^3) replaces the gradient passes of the line search
             bool algebraic = false;
-            if (use_pc && (m == 2 || m == 4) && need_model) {
+            if (logistic) {
+                // the separable term is not a polynomial: start the backtracking
+                // at the full step, shortened to stay inside the domain
+                std::vector<double> cap(B);
+                TK_HIP_CHECK(vec_step_cap(alpha, sb.x, y, cx.y_stride, lam, sb.stats, B, n, st));
+                if ((rc = sync_copy(cap.data(), sb.stats, B))) return rc;
+                for (int64_t b = 0; b < B; ++b)
+                    if (!ps[b].done) t[b] = std::min(1.0, 0.99 * cap[b]);
+            } else if (use_pc && (m == 2 || m == 4) && need_model) {
                 // exact model of D along x: s2 from the assembled Hessian, and
                 // for m = 4 the cubic and quartic terms from one pass giving
                 // dv = K . x^3 (D is a quartic polynomial in the step length)
@@ -1021,12 +1188,12 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                 if (m == 4) {
                     if (algebraic) {   // r = 3 K x^2 alpha, dv = K x^3
                         if ((rc = run_contract(Kp, dt, n, m, sb.x, alpha, B, sb.dv, sb.r, ACC_PLAIN64, sb.cw,
-                                               sb.cw_bytes, st)))
+                                               sb.cw_bytes, st, 0, nullptr, cx.k_stride)))
                             return rc;
                     } else {
                         const int pm = dt == TK_F64 ? ACC_PLAIN64 : ACC_PLAIN32;
                         if ((rc = run_contract(Kp, dt, n, m, sb.x, nullptr, B, sb.dv, nullptr, pm, sb.cw, sb.cw_bytes,
-                                               st)))
+                                               st, 0, nullptr, cx.k_stride)))
                             return rc;
                     }
                     passes++;
@@ -1053,7 +1220,7 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                 TK_HIP_CHECK(vec_lin2(alpha, sb.x, one, tc, sb.at, B, n, st));   // at = alpha + t x
                 if (algebraic) {   // gt = g + t J x + t^2 r + t^3 dv
                     TK_HIP_CHECK(vec_poly3(sb.g, sb.z, sb.r, sb.dv, tc, sb.gt, B, n, st));
-                    TK_HIP_CHECK(vec_grad(sb.gt, sb.at, y, lam, sb.hd, sb.stats, B, n, st));
+                    TK_HIP_CHECK(vec_grad(sb.gt, sb.at, y, lam, sb.hd, sb.stats, B, n, st, cx.y_stride));
                     if ((rc = sync_copy(hst.data(), sb.stats, B * 4))) return rc;
                 } else if ((rc = gradient(Kp, dt, sb.at, sb.gt, sb.hd, hst))) {
                     return rc;
@@ -1063,7 +1230,7 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                 for (int64_t b = 0; b < B; ++b) {
                     keep_c.c[b] = 1.0;
                     if (!ls[b]) continue;
-                    const double Dn = inv_m * hst[4 * b] + 0.5 * ps[b].lam * hst[4 * b + 1] - hst[4 * b + 2];
+                    const double Dn = dual_of(&hst[4 * b], ps[b].lam);
                     const bool ok = std::isfinite(Dn) &&
                                     (Dn <= ps[b].D + 1e-4 * t[b] * slope[b] ||
                                      // below rounding of D: accept if the gradient norm decreased
@@ -1088,10 +1255,12 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                         t[b] *= 0.5;
                         if (t[b] < 1e-14) {   // no decrease visible: rounding floor of D
                             ls[b] = false;
-                            if (accurate)
+                            if (accurate) {
                                 ps[b].done = true;
-                            else
+                                if (reduced) reason[b] = TK_STOP_FLOOR;   // ... of the rounded tensor
+                            } else {
                                 floor_plain = true;   // ... of the plain passes: go on compensated
+                            }
                         }
                     }
                 }
@@ -1118,20 +1287,35 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
             if ((rc = gradient(Kp, dt, alpha, sb.g, sb.grad, hst))) return rc;
             take_stats();
         }
+        bool restored = false;
         for (int64_t b = 0; b < B; ++b) {
             ProblemState &s = ps[b];
-            if (phases == 2 && phase == 0) {
-                if (std::isfinite(kept_gn[b])) {   // the polish starts from the kept iterate
-                    s.status = TK_OK;
+            if (reduced) {
+                if (std::isfinite(kept_gn[b]) && kept_gn[b] < s.gn) {   // back to the kept iterate
+                    if (s.status == TK_ENAN) s.status = TK_OK;
                     TK_HIP_CHECK(hipMemcpyAsync(alpha + b * n, sb.best + b * n, n * sizeof(double),
                                                 hipMemcpyDeviceToDevice, st));
-                } else if (s.status == TK_ENAN) {   // restart the polish from zero
+                    restored = true;
+                } else if (phases == 2 && s.status == TK_ENAN) {   // restart the polish from zero
                     s.status = TK_OK;
                     TK_HIP_CHECK(hipMemsetAsync(alpha + b * n, 0, n * sizeof(double), st));
                 }
-                continue;
             }
-            if (s.status == TK_OK && o.fixed_iters <= 0 && !(s.gn <= tol * s.lam * s.an)) s.status = TK_ENOCONV;
+        }
+        if (phases == 2 && phase == 0) {
+            for (int64_t b = 0; b < B; ++b) reason[b] = TK_STOP_TOL;
+            continue;   // the polish follows
+        }
+        if (restored) {   // statistics of the returned iterates
+            if ((rc = gradient(Kp, dt, alpha, sb.g, sb.grad, hst))) return rc;
+            take_stats();
+        }
+        for (int64_t b = 0; b < B; ++b) {
+            ProblemState &s = ps[b];
+            if (s.status == TK_OK && (s.gn == 0 || s.gn <= tol * s.lam * s.an)) reason[b] = TK_STOP_TOL;
+            if (s.status == TK_OK && o.fixed_iters <= 0 && reason[b] == TK_STOP_TOL && s.gn != 0 &&
+                !(s.gn <= tol * s.lam * s.an))
+                s.status = TK_ENOCONV;
         }
     }
     int overall = TK_OK;
@@ -1146,6 +1330,7 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
         inf.status = ps[b].status;
         inf.hess_passes = hess_passes;
         inf.precond_updates = pc_updates[b];
+        inf.stop_reason = ps[b].status == TK_OK ? reason[b] : TK_STOP_TOL;
         if (ps[b].status != TK_OK) overall = ps[b].status;
     }
     return overall;
@@ -1156,17 +1341,72 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
 
 extern "C" {
 
-int tk_solve_workspace(int64_t n, int m, int64_t B, int dtype, size_t *h_bytes)
+int tk_solve_workspace_ex(int64_t n, int m, int64_t B, int dtype, int64_t support_d, size_t *h_bytes)
 {
     int rc;
     if ((rc = check_nm(n, m))) return rc;
     if ((rc = check_dtype(dtype))) return rc;
     if (B < 1) return fail(TK_EINVAL, "B must be >= 1");
+    if (support_d < 0) return fail(TK_EINVAL, "support_d must be >= 0");
     if (!h_bytes) return fail(TK_EINVAL, "null output pointer");
     const int64_t bb = B < kMaxCoefs ? B : kMaxCoefs;
-    *h_bytes = solve_ws(n, m, bb, dtype);
+    *h_bytes = solve_ws(n, m, bb, dtype, support_d);
     return TK_OK;
 }
+
+int tk_solve_workspace(int64_t n, int m, int64_t B, int dtype, size_t *h_bytes)
+{
+    return tk_solve_workspace_ex(n, m, B, dtype, 0, h_bytes);
+}
+
+}  // extern "C"
+
+namespace tk {
+namespace {
+
+// Options shared by the single-tensor and the multi-tensor solves: defaults,
+// validation, and the solve context they imply.
+int prepare_solve(const tk_solve_opts *h_opts, tk_solve_opts &o, SolveCtx &cx)
+{
+    tk_solve_opts_default(&o);
+    if (h_opts) o = *h_opts;
+    if (o.polish_K && o.polish_dtype != TK_F64) return fail(TK_EINVAL, "the polish tensor must be FP64");
+    if (o.loss != TK_LOSS_SQUARE && o.loss != TK_LOSS_LOGISTIC) return fail(TK_EINVAL, "unknown loss %d", o.loss);
+    if (o.support_stop < 0) return fail(TK_EINVAL, "support_stop must be >= 0");
+    if (o.support_stop > 0 && (!o.support_X || o.support_d < 1))
+        return fail(TK_EINVAL, "support_stop needs the points (support_X) and their dimension (support_d)");
+    cx.loss = o.loss;
+    cx.support_stop = o.support_stop;
+    cx.sX = o.support_stop > 0 ? o.support_X : nullptr;
+    cx.sd = o.support_stop > 0 ? o.support_d : 0;
+    return TK_OK;
+}
+
+// Checks of the responses and of the warm start before any pass: finite
+// values; for the logistic loss labels in {-1, +1} and a warm start inside the
+// dual's domain.
+int check_solve_inputs(const tk_solve_opts &o, const double *d_y, int64_t ylen, const double *d_alpha,
+                       int64_t alen, const double *h_lams, int64_t nlam, void *d_work, hipStream_t st)
+{
+    int *flag = reinterpret_cast<int *>(d_work);
+    int bad[2] = {0, 0};
+    TK_HIP_CHECK(hipMemsetAsync(flag, 0, 2 * sizeof(int), st));
+    TK_HIP_CHECK(vec_nonfinite(d_y, ylen, flag, st));
+    if (o.warm_start) TK_HIP_CHECK(vec_nonfinite(d_alpha, alen, flag, st));
+    if (o.loss == TK_LOSS_LOGISTIC) TK_HIP_CHECK(vec_check_labels(d_y, ylen, flag + 1, st));
+    TK_HIP_CHECK(hipMemcpyAsync(bad, flag, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    TK_HIP_CHECK(hipStreamSynchronize(st));
+    if (bad[0]) return fail(TK_ENAN, "non-finite value in y%s", o.warm_start ? " or in the warm start" : "");
+    if (bad[1]) return fail(TK_EINVAL, "the logistic loss needs labels y in {-1, +1}");
+    (void)h_lams;
+    (void)nlam;
+    return TK_OK;
+}
+
+}  // namespace
+}  // namespace tk
+
+extern "C" {
 
 int tk_solve_dual(const void *d_K, int dtype, int64_t n, int m, const double *d_y, const double *h_lambdas,
                   int64_t B, const tk_solve_opts *h_opts, double *d_alpha, tk_solve_info *h_info, void *d_work,
@@ -1178,16 +1418,27 @@ int tk_solve_dual(const void *d_K, int dtype, int64_t n, int m, const double *d_
     if (B < 1) return fail(TK_EINVAL, "B must be >= 1");
     if (!d_K || !d_y || !h_lambdas || !d_alpha || !h_info) return fail(TK_EINVAL, "null pointer");
     tk_solve_opts o;
-    tk_solve_opts_default(&o);
-    if (h_opts) o = *h_opts;
-    if (o.polish_K && o.polish_dtype != TK_F64) return fail(TK_EINVAL, "the polish tensor must be FP64");
+    SolveCtx cx;
+    if ((rc = prepare_solve(h_opts, o, cx))) return rc;
     for (int64_t b = 0; b < B; ++b)
         if (!(h_lambdas[b] > 0) || !std::isfinite(h_lambdas[b]))
             return fail(TK_EINVAL, "lambda[%lld] must be positive and finite", (long long)b);
     const int64_t bb = B < kMaxCoefs ? B : kMaxCoefs;
-    const size_t need = solve_ws(n, m, bb, dtype);
+    const size_t need = solve_ws(n, m, bb, dtype, cx.sd);
     if (work_bytes < need || !d_work) return fail(TK_ENOMEM, "solve workspace of %zu bytes < %zu", work_bytes, need);
     hipStream_t st = as_stream(stream);
+    if ((rc = check_solve_inputs(o, d_y, n, d_alpha, B * n, h_lambdas, B, d_work, st))) return rc;
+    // cold starts: alpha = 0 (square loss), the centre of the domain (logistic)
+    auto cold = [&](double *a, const double *lams, int64_t nb) -> int {
+        if (o.loss == TK_LOSS_LOGISTIC) {
+            Coefs lc{};
+            for (int64_t b = 0; b < nb; ++b) lc.c[b] = lams[b];
+            TK_HIP_CHECK(vec_logistic_start(d_y, 0, lc, a, nb, n, st));
+        } else {
+            TK_HIP_CHECK(hipMemsetAsync(a, 0, (size_t)nb * n * sizeof(double), st));
+        }
+        return TK_OK;
+    };
     int overall = TK_OK;
     if (B > 1 && o.continuation) {
         // lambda path: from the largest lambda down, each solve starts from the
@@ -1197,16 +1448,16 @@ int tk_solve_dual(const void *d_K, int dtype, int64_t n, int m, const double *d_
         std::stable_sort(order.begin(), order.end(),
                          [&](int64_t u, int64_t v) { return h_lambdas[u] > h_lambdas[v]; });
         std::vector<Precond> pc(1);
-        SolveBuffers sb = carve(d_work, n, m, 1, work_bytes);
+        SolveBuffers sb = carve(d_work, n, m, 1, work_bytes, cx.sd);
         int64_t prev = -1;
         for (int64_t idx = 0; idx < B; ++idx) {
             const int64_t b = order[idx];
             double *a = d_alpha + b * n;
             if (prev >= 0 && !o.warm_start)
                 TK_HIP_CHECK(hipMemcpyAsync(a, d_alpha + prev * n, n * sizeof(double), hipMemcpyDeviceToDevice, st));
-            else if (prev < 0 && !o.warm_start)
-                TK_HIP_CHECK(hipMemsetAsync(a, 0, n * sizeof(double), st));
-            rc = solve_batch(d_K, dtype, n, m, d_y, h_lambdas + b, 1, o, a, h_info + b, sb, st, pc);
+            else if (prev < 0 && !o.warm_start && (rc = cold(a, h_lambdas + b, 1)))
+                return rc;
+            rc = solve_batch(d_K, dtype, n, m, d_y, h_lambdas + b, 1, o, a, h_info + b, sb, st, pc, cx);
             if (rc != TK_OK && rc != TK_ENOCONV && rc != TK_ENAN) return rc;
             if (rc != TK_OK) overall = rc;
             prev = b;
@@ -1215,15 +1466,135 @@ int tk_solve_dual(const void *d_K, int dtype, int64_t n, int m, const double *d_
         for (int64_t b0 = 0; b0 < B; b0 += kMaxCoefs) {
             const int64_t nb = (B - b0) < kMaxCoefs ? (B - b0) : kMaxCoefs;
             double *a = d_alpha + b0 * n;
-            if (!o.warm_start) TK_HIP_CHECK(hipMemsetAsync(a, 0, (size_t)nb * n * sizeof(double), st));
-            SolveBuffers sb = carve(d_work, n, m, nb, work_bytes);
+            if (!o.warm_start && (rc = cold(a, h_lambdas + b0, nb))) return rc;
+            SolveBuffers sb = carve(d_work, n, m, nb, work_bytes, cx.sd);
             std::vector<Precond> pc(nb);
-            rc = solve_batch(d_K, dtype, n, m, d_y, h_lambdas + b0, nb, o, a, h_info + b0, sb, st, pc);
+            rc = solve_batch(d_K, dtype, n, m, d_y, h_lambdas + b0, nb, o, a, h_info + b0, sb, st, pc, cx);
             if (rc != TK_OK && rc != TK_ENOCONV && rc != TK_ENAN) return rc;
             if (rc != TK_OK) overall = rc;
         }
     }
     if (overall == TK_ENOCONV) fail(TK_ENOCONV, "at least one lambda did not reach the tolerance");
+    if (overall == TK_ENAN) fail(TK_ENAN, "non-finite values met during the solve");
+    return overall;
+}
+
+int tk_packed_stride(int64_t n, int m, int dtype, int64_t *h_stride)
+{
+    int rc;
+    int64_t c;
+    if ((rc = tk_packed_count(n, m, &c))) return rc;
+    if ((rc = check_dtype(dtype))) return rc;
+    if (!h_stride) return fail(TK_EINVAL, "null output pointer");
+    const int64_t per = 256 / (int64_t)dtype_size(dtype);   // entries per 256 bytes
+    if (c > INT64_MAX - per) return fail(TK_EOVERFLOW, "stride overflows int64");
+    *h_stride = (c + per - 1) / per * per;
+    return TK_OK;
+}
+
+int tk_build_packed_multi(const double *d_X, int64_t T, int64_t n, int64_t d, int m, int kernel, double kparam,
+                          int dtype, void *d_K, int64_t k_stride, void *stream)
+{
+    int rc;
+    if (T < 1 || T > 65535) return fail(TK_EINVAL, "T must be in [1, 65535]");
+    int64_t need;
+    if ((rc = tk_packed_stride(n, m, dtype, &need))) return rc;
+    if (k_stride < need) return fail(TK_EINVAL, "k_stride %lld is below tk_packed_stride (%lld)", (long long)k_stride,
+                                     (long long)need);
+    if (((size_t)k_stride * dtype_size(dtype)) % 16) return fail(TK_EINVAL, "k_stride must keep 16-byte alignment");
+    if (!d_X || !d_K) return fail(TK_EINVAL, "null device pointer");
+    for (int64_t t = 0; t < T; ++t) {
+        rc = tk_build_packed_tensor(d_X + t * n * d, n, d, m, kernel, kparam, dtype,
+                                    reinterpret_cast<unsigned char *>(d_K) + (size_t)t * k_stride * dtype_size(dtype),
+                                    stream);
+        if (rc) return rc;
+    }
+    return TK_OK;
+}
+
+int tk_contract_multi(const void *d_K, int dtype, int64_t n, int m, int64_t T, int64_t k_stride,
+                      const double *d_alpha, double *d_g, int acc, void *d_work, size_t work_bytes, void *stream)
+{
+    int rc;
+    if ((rc = check_nm(n, m))) return rc;
+    if ((rc = check_dtype(dtype))) return rc;
+    if (T < 1 || T > 65535) return fail(TK_EINVAL, "T must be in [1, 65535]");
+    int64_t need;
+    if ((rc = tk_packed_stride(n, m, dtype, &need))) return rc;
+    if (k_stride < need) return fail(TK_EINVAL, "k_stride below tk_packed_stride");
+    if (((size_t)k_stride * dtype_size(dtype)) % 16) return fail(TK_EINVAL, "k_stride must keep 16-byte alignment");
+    if (!d_K || !d_alpha || !d_g) return fail(TK_EINVAL, "null device pointer");
+    int mode;
+    if ((rc = mode_for(dtype, acc, false, &mode))) return rc;
+    return run_contract(d_K, dtype, n, m, d_alpha, nullptr, T, d_g, nullptr, mode, d_work, work_bytes,
+                        as_stream(stream), 1, nullptr, k_stride);
+}
+
+int tk_solve_dual_multi(const void *d_K, int dtype, int64_t n, int m, int64_t T, int64_t k_stride,
+                        const double *d_y, const double *h_lambdas, int64_t L, const tk_solve_opts *h_opts,
+                        double *d_alpha, tk_solve_info *h_info, void *d_work, size_t work_bytes, void *stream)
+{
+    int rc;
+    if ((rc = check_nm(n, m))) return rc;
+    if ((rc = check_dtype(dtype))) return rc;
+    if (T < 1 || T > 65535 || L < 1) return fail(TK_EINVAL, "T must be in [1, 65535] and L >= 1");
+    int64_t need_stride;
+    if ((rc = tk_packed_stride(n, m, dtype, &need_stride))) return rc;
+    if (k_stride < need_stride) return fail(TK_EINVAL, "k_stride below tk_packed_stride");
+    if (((size_t)k_stride * dtype_size(dtype)) % 16) return fail(TK_EINVAL, "k_stride must keep 16-byte alignment");
+    if (!d_K || !d_y || !h_lambdas || !d_alpha || !h_info) return fail(TK_EINVAL, "null pointer");
+    tk_solve_opts o;
+    SolveCtx cx;
+    if ((rc = prepare_solve(h_opts, o, cx))) return rc;
+    if (o.polish_K) return fail(TK_EINVAL, "the multi-tensor solve takes no polish tensor");
+    if (o.support_stop > 0) return fail(TK_EINVAL, "the multi-tensor solve has no stable-support stop");
+    for (int64_t l = 0; l < L; ++l)
+        if (!(h_lambdas[l] > 0) || !std::isfinite(h_lambdas[l]))
+            return fail(TK_EINVAL, "lambda[%lld] must be positive and finite", (long long)l);
+    cx.k_stride = k_stride;
+    cx.y_stride = n;
+    const int64_t bb = T < kMaxCoefs ? T : kMaxCoefs;
+    const size_t need = solve_ws(n, m, bb, dtype);
+    if (work_bytes < need || !d_work) return fail(TK_ENOMEM, "solve workspace of %zu bytes < %zu", work_bytes, need);
+    hipStream_t st = as_stream(stream);
+    if ((rc = check_solve_inputs(o, d_y, T * n, d_alpha, L * T * n, h_lambdas, L, d_work, st))) return rc;
+    std::vector<int64_t> order(L);
+    for (int64_t l = 0; l < L; ++l) order[l] = l;
+    std::stable_sort(order.begin(), order.end(), [&](int64_t u, int64_t v) { return h_lambdas[u] > h_lambdas[v]; });
+    int overall = TK_OK;
+    // draws in lock step (up to 64 per batch, every pass shared), lambdas by
+    // continuation from the largest down; each draw keeps its Hessian and
+    // preconditioner from lambda to lambda
+    for (int64_t t0 = 0; t0 < T; t0 += kMaxCoefs) {
+        const int64_t nb = (T - t0) < kMaxCoefs ? (T - t0) : kMaxCoefs;
+        SolveBuffers sb = carve(d_work, n, m, nb, work_bytes);
+        std::vector<Precond> pc(nb);
+        const void *Kb = reinterpret_cast<const unsigned char *>(d_K) + (size_t)t0 * k_stride * dtype_size(dtype);
+        const double *yb = d_y + t0 * n;
+        int64_t prev = -1;
+        for (int64_t idx = 0; idx < L; ++idx) {
+            const int64_t l = order[idx];
+            double *a = d_alpha + (l * T + t0) * n;
+            std::vector<double> lams(nb, h_lambdas[l]);
+            if (!o.warm_start) {
+                if (prev >= 0) {
+                    TK_HIP_CHECK(hipMemcpyAsync(a, d_alpha + (prev * T + t0) * n, (size_t)nb * n * sizeof(double),
+                                                hipMemcpyDeviceToDevice, st));
+                } else if (o.loss == TK_LOSS_LOGISTIC) {
+                    Coefs lc{};
+                    for (int64_t b = 0; b < nb; ++b) lc.c[b] = h_lambdas[l];
+                    TK_HIP_CHECK(vec_logistic_start(yb, n, lc, a, nb, n, st));
+                } else {
+                    TK_HIP_CHECK(hipMemsetAsync(a, 0, (size_t)nb * n * sizeof(double), st));
+                }
+            }
+            rc = solve_batch(Kb, dtype, n, m, yb, lams.data(), nb, o, a, h_info + l * T + t0, sb, st, pc, cx);
+            if (rc != TK_OK && rc != TK_ENOCONV && rc != TK_ENAN) return rc;
+            if (rc != TK_OK) overall = rc;
+            prev = l;
+        }
+    }
+    if (overall == TK_ENOCONV) fail(TK_ENOCONV, "at least one problem did not reach the tolerance");
     if (overall == TK_ENAN) fail(TK_ENAN, "non-finite values met during the solve");
     return overall;
 }
@@ -1247,6 +1618,41 @@ int tk_predict(const double *d_W, int64_t d, int64_t B, const double *d_Xq, int6
     // f[b][q] = sum_j W[b][j] Xq[q][j]
     hipError_t e = launch_gemm(d_W, d, d_Xq, 1, d, d_f, N, B, N, d, 1, as_stream(stream));
     if (e != hipSuccess) return fail(TK_EHIP, "gemm failed: %s", hipGetErrorString(e));
+    return TK_OK;
+}
+
+int tk_predict_kernel_workspace(int64_t n, int m, int64_t B, int64_t N, size_t *h_bytes)
+{
+    if (n < 1 || B < 1 || N < 1) return fail(TK_EINVAL, "sizes must be >= 1");
+    if (m < 2 || (m & 1) || m > kMaxOrder) return fail(TK_EINVAL, "m must be even and in [2, %d]", kMaxOrder);
+    if (!h_bytes) return fail(TK_EINVAL, "null output pointer");
+    const int64_t tuples = checked_binom(n + m - 2, m - 1);
+    if (tuples < 0 || tuples > ((int64_t)1 << 40)) return fail(TK_EOVERFLOW, "too many (m-1)-tuples");
+    const int64_t bb = B < predict_max_batch() ? B : predict_max_batch();
+    *h_bytes = (size_t)predict_groups(n, m, N) * (size_t)bb * (size_t)N * sizeof(double);
+    return TK_OK;
+}
+
+int tk_predict_kernel(const double *d_X, int64_t n, int64_t d, int m, int kernel, double kparam,
+                      const double *d_alpha, int64_t B, const double *d_Xq, int64_t N, double *d_f, void *d_work,
+                      size_t work_bytes, void *stream)
+{
+    int rc;
+    size_t need;
+    if ((rc = tk_predict_kernel_workspace(n, m, B, N, &need))) return rc;
+    if (d < 1 || d > INT32_MAX || n > INT32_MAX) return fail(TK_EINVAL, "n and d must be in [1, 2^31)");
+    if (N > (int64_t)65535 * 64) return fail(TK_EINVAL, "N must be at most %d", 65535 * 64);
+    if (kernel == TK_POLY) {
+        if (!(kparam >= 1.0) || kparam != std::floor(kparam) || kparam > 64)
+            return fail(TK_EINVAL, "polynomial degree must be an integer in [1, 64]");
+    } else if (kernel != TK_LINEAR && kernel != TK_EXP) {
+        return fail(TK_EINVAL, "unknown kernel %d", kernel);
+    }
+    if (!d_X || !d_alpha || !d_Xq || !d_f) return fail(TK_EINVAL, "null device pointer");
+    if (work_bytes < need || !d_work) return fail(TK_ENOMEM, "workspace of %zu bytes < %zu", work_bytes, need);
+    hipError_t e = launch_predict_kernel(d_X, n, d, m, kernel, kparam, d_alpha, B, d_Xq, N, d_f,
+                                         reinterpret_cast<double *>(d_work), as_stream(stream));
+    if (e != hipSuccess) return fail(TK_EHIP, "prediction failed: %s", hipGetErrorString(e));
     return TK_OK;
 }
 
@@ -1341,6 +1747,20 @@ int tk_dmse_dlambda(const void *d_K, int dtype, int64_t n, int m, const double *
         e = (x);                                                                    \
         if (e != hipSuccess) return fail(TK_EHIP, "%s: %s", #x, hipGetErrorString(e)); \
     } while (0)
+    {
+        // non-finite inputs end the call before any pass
+        int *flag = reinterpret_cast<int *>(sc);
+        int bad = 0;
+        TK_CHK(hipMemsetAsync(flag, 0, sizeof(int), st));
+        TK_CHK(vec_nonfinite(d_alpha, n, flag, st));
+        TK_CHK(vec_nonfinite(d_X, n * d, flag, st));
+        TK_CHK(vec_nonfinite(d_Xval, nval * d, flag, st));
+        TK_CHK(vec_nonfinite(d_yval, nval, flag, st));
+        TK_CHK(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+        TK_CHK(hipStreamSynchronize(st));
+        if (bad) return fail(TK_ENAN, "non-finite value in alpha, X, X_val or y_val");
+        if (!std::isfinite(lambda)) return fail(TK_EINVAL, "lambda must be finite");
+    }
     // u = X^T alpha, w = u^{m-1}
     TK_CHK(launch_gemm(d_alpha, n, d_X, d, 1, u, d, 1, d, n, 1, st));
     TK_CHK(launch_gemm(d_alpha, n, d_X, d, 1, wv, d, 1, d, n, m - 1, st));
@@ -1372,6 +1792,7 @@ int tk_dmse_dlambda(const void *d_K, int dtype, int64_t n, int m, const double *
     const double r0 = std::sqrt(rr);
     const int maxit = max_cg > 0 ? max_cg : 5000;
     const double tol = cg_tol > 0 ? cg_tol : 1e-12;
+    bool curvature_lost = false;
     for (int j = 0; j < maxit && std::sqrt(rr) > tol * r0 && rr > 0; ++j) {
         // compensated directional derivatives on FP64 storage: at the dual
         // optimum the products cancel heavily and CG amplifies their error
@@ -1382,7 +1803,10 @@ int tk_dmse_dlambda(const void *d_K, int dtype, int64_t n, int m, const double *
         double dhd;
         TK_CHK(hipMemcpyAsync(&dhd, sc, sizeof(double), hipMemcpyDeviceToHost, st));
         TK_CHK(hipStreamSynchronize(st));
-        if (!(dhd > 0)) break;
+        if (!(dhd > 0)) {
+            curvature_lost = true;
+            break;
+        }
         Coefs a{};
         a.c[0] = rr / dhd;
         TK_CHK(vec_cg_update(x, r, dv, hd, a, sc, 1, n, st));
@@ -1401,6 +1825,12 @@ int tk_dmse_dlambda(const void *d_K, int dtype, int64_t n, int m, const double *
     *h_dmse = -hs[0];
     if (d_z) TK_CHK(hipMemcpyAsync(d_z, x, n * sizeof(double), hipMemcpyDeviceToDevice, st));
 #undef TK_CHK
+    if (!std::isfinite(*h_dmse) || !std::isfinite(*h_mse)) return fail(TK_ENAN, "non-finite dMSE/dlambda");
+    // the outputs hold the last CG iterate either way; the status says whether
+    // CG reached its tolerance
+    if (curvature_lost || (rr > 0 && std::sqrt(rr) > tol * r0))
+        return fail(TK_ENOCONV, "CG stopped at relative residual %.3e (tolerance %.3e)%s", std::sqrt(rr) / r0, tol,
+                    curvature_lost ? " after losing positive curvature" : "");
     return TK_OK;
 }
 

@@ -130,7 +130,20 @@ std::vector<int64_t> make_plan_host(int q, int64_t n, int64_t waves)
 
 std::mutex g_plan_mu;
 std::map<std::tuple<int, int, int64_t, int>, int64_t *> g_plans;
+std::mutex g_hplan_mu;
+std::map<std::tuple<int, int64_t, int>, std::vector<int64_t>> g_hplans;
 }  // namespace
+
+const std::vector<int64_t> &pass_plan_host(int q, int64_t n, int groups)
+{
+    // entries of the map are never erased or modified once made, so the
+    // returned vector (and its data) stays valid for the life of the process
+    std::lock_guard<std::mutex> lk(g_hplan_mu);
+    const auto key = std::make_tuple(q, n, groups);
+    auto it = g_hplans.find(key);
+    if (it != g_hplans.end()) return it->second;
+    return g_hplans.emplace(key, make_plan_host(q, n, (int64_t)groups * 4)).first->second;
+}
 
 const int64_t *pass_plan(int q, int64_t n, int groups, int *err)
 {
@@ -143,7 +156,7 @@ const int64_t *pass_plan(int q, int64_t n, int groups, int *err)
     std::lock_guard<std::mutex> lk(g_plan_mu);
     auto it = g_plans.find(key);
     if (it != g_plans.end()) return it->second;
-    const std::vector<int64_t> h = make_plan_host(q, n, (int64_t)groups * 4);
+    const std::vector<int64_t> &h = pass_plan_host(q, n, groups);
     int64_t *d = nullptr;
     if (hipMalloc((void **)&d, h.size() * sizeof(int64_t)) != hipSuccess ||
         hipMemcpy(d, h.data(), h.size() * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess) {

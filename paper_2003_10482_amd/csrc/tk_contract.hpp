@@ -1,6 +1,8 @@
 // Host-visible pieces of the contraction kernels (parameters and launchers).
 #pragma once
 
+#include <vector>
+
 #include "tk_common.hpp"
 
 namespace tk {
@@ -45,6 +47,8 @@ int pass_resident(int q, int in_kind, int mode, int hv, int bt, int64_t n);
 int pass_groups(int q, int64_t n, int64_t count, int resident, int64_t tiles);
 // Device copy of the balanced work plan of one pass (cached per (n, q, groups)).
 const int64_t *pass_plan(int q, int64_t n, int groups, int *err);
+// Host copy of the same plan (groups * 4 + 1 entries; cached, never freed).
+const std::vector<int64_t> &pass_plan_host(int q, int64_t n, int groups);
 hipError_t launch_pass(int q, int in_kind, int mode, int hv, int bt, const PairParams &pp,
                        int groups, hipStream_t st);
 // per accumulation mode (separate translation units)

@@ -13,6 +13,13 @@ hipError_t launch_support(const double *W, int64_t d, int64_t B, uint8_t *mask, 
                           hipStream_t st);
 hipError_t launch_gather(const double *X, int64_t N, int64_t d, const int64_t *idx, int64_t l,
                          double *out, int *bad, hipStream_t st);
+// General-kernel prediction f[b][q] = sum_T c(T) alpha_b^T k(x_T, xq_q) (part:
+// predict_groups(n, m, N) * min(B, predict_max_batch()) * N doubles of workspace).
+hipError_t launch_predict_kernel(const double *X, int64_t n, int64_t d, int m, int kernel, double kparam,
+                                 const double *alpha, int64_t B, const double *Xq, int64_t N, double *f,
+                                 double *part, hipStream_t st);
+int64_t predict_groups(int64_t n, int m, int64_t N);
+int predict_max_batch();
 hipError_t launch_build(const double *X, int n, int d, int m, int kernel, double kparam, int dtype,
                         void *K, hipStream_t st);
 

@@ -21,9 +21,10 @@ __device__ DD block_sum_dd(DD v, DD *sh)
     return r;
 }
 
-// grad_b = g_b + lam_b alpha_b - y ; stats_b = [alpha.g, alpha.alpha, y.alpha, grad.grad]
+// grad_b = g_b + lam_b alpha_b - y_b ; stats_b = [alpha.g, alpha.alpha, y.alpha, grad.grad]
+// (y_b = y + b * y_stride: one response shared by all problems, or one each)
 __global__ void __launch_bounds__(256) grad_kernel(const double *__restrict__ g, const double *__restrict__ alpha,
-                                                   const double *__restrict__ y, Coefs lam,
+                                                   const double *__restrict__ y, int64_t y_stride, Coefs lam,
                                                    double *__restrict__ grad, double *__restrict__ stats,
                                                    int64_t n)
 {
@@ -33,7 +34,7 @@ __global__ void __launch_bounds__(256) grad_kernel(const double *__restrict__ g,
     DD s_ag{0, 0}, s_aa{0, 0}, s_ya{0, 0}, s_gg{0, 0};
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
         const int64_t j = (int64_t)b * n + i;
-        const double a = alpha[j], gv = g[j], yv = y[i];
+        const double a = alpha[j], gv = g[j], yv = y[(int64_t)b * y_stride + i];
         // grad = g + lam a - y, formed with one rounding of the exact sum
         DD t{0, 0};
         dd_fma(t, l, a);
@@ -54,6 +55,120 @@ __global__ void __launch_bounds__(256) grad_kernel(const double *__restrict__ g,
         stats[b * 4 + 2] = r2.hi + r2.lo;
         stats[b * 4 + 3] = r3.hi + r3.lo;
     }
+}
+
+// Logistic loss (the dual's separable term through the loss's Fenchel
+// conjugate): with p = lam_b y_i alpha_i,
+//   grad_b = g_b + y (log p - log(1 - p)),  hdiag_b = lam_b / (p (1 - p)),
+//   stats_b = [alpha.g, alpha.alpha, S, grad.grad],  S = sum p log p + (1 - p) log(1 - p),
+// so that D = alpha.g / m + S / lam_b; S = +inf when some p lies outside (0, 1).
+__global__ void __launch_bounds__(256) grad_logistic_kernel(const double *__restrict__ g,
+                                                            const double *__restrict__ alpha,
+                                                            const double *__restrict__ y, int64_t y_stride,
+                                                            Coefs lam, double *__restrict__ grad,
+                                                            double *__restrict__ hdiag,
+                                                            double *__restrict__ stats, int64_t n)
+{
+    __shared__ DD sh[256];
+    const int b = blockIdx.x;
+    const double l = lam.c[b];
+    DD s_ag{0, 0}, s_aa{0, 0}, s_S{0, 0}, s_gg{0, 0};
+    double outside = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const int64_t j = (int64_t)b * n + i;
+        const double a = alpha[j], gv = g[j], yv = y[(int64_t)b * y_stride + i];
+        const double p = l * yv * a;
+        double gr, h, sv;
+        if (p > 0.0 && p < 1.0) {
+            const double lp = log(p), lq = log1p(-p);
+            gr = gv + yv * (lp - lq);
+            h = l / (p * (1.0 - p));
+            sv = p * lp + (1.0 - p) * lq;
+        } else {
+            gr = gv;
+            h = l;
+            sv = 0.0;
+            outside = 1.0;
+        }
+        grad[j] = gr;
+        hdiag[j] = h;
+        dd_fma(s_ag, a, gv);
+        dd_fma(s_aa, a, a);
+        s_S = dd_add(s_S, DD{sv, 0.0});
+        dd_fma(s_gg, gr, gr);
+    }
+    DD r0 = block_sum_dd(s_ag, sh), r1 = block_sum_dd(s_aa, sh), r2 = block_sum_dd(s_S, sh),
+       r3 = block_sum_dd(s_gg, sh), r4 = block_sum_dd(DD{outside, 0.0}, sh);
+    if (threadIdx.x == 0) {
+        stats[b * 4 + 0] = r0.hi + r0.lo;
+        stats[b * 4 + 1] = r1.hi + r1.lo;
+        stats[b * 4 + 2] = r4.hi > 0 ? INFINITY : r2.hi + r2.lo;
+        stats[b * 4 + 3] = r3.hi + r3.lo;
+    }
+}
+
+// Largest step t with lam_b y_i (alpha_i + t x_i) inside [0, 1] for every i
+// (the logistic dual's domain): out_b = min over i of -p/dp (dp < 0) or
+// (1 - p)/dp (dp > 0), +inf when no component moves.
+__global__ void __launch_bounds__(256) step_cap_kernel(const double *__restrict__ alpha, const double *__restrict__ x,
+                                                       const double *__restrict__ y, int64_t y_stride, Coefs lam,
+                                                       double *__restrict__ out, int64_t n)
+{
+    __shared__ double sh[256];
+    const int b = blockIdx.x;
+    const double l = lam.c[b];
+    double t = INFINITY;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const int64_t j = (int64_t)b * n + i;
+        const double yv = y[(int64_t)b * y_stride + i];
+        const double p = l * yv * alpha[j], dp = l * yv * x[j];
+        if (dp < 0) t = fmin(t, -p / dp);
+        else if (dp > 0) t = fmin(t, (1.0 - p) / dp);
+    }
+    sh[threadIdx.x] = t;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + st]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[b] = sh[0];
+}
+
+// alpha_b = y_b / (2 lam_b): the centre of the logistic dual's domain (p = 1/2)
+__global__ void __launch_bounds__(256) logistic_start_kernel(const double *__restrict__ y, int64_t y_stride,
+                                                             Coefs lam, double *__restrict__ alpha, int64_t n)
+{
+    const int b = blockIdx.y;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        alpha[(int64_t)b * n + i] = y[(int64_t)b * y_stride + i] / (2.0 * lam.c[b]);
+}
+
+// flag |= (y_i not in {-1, +1}) for the logistic loss's labels
+__global__ void labels_kernel(const double *__restrict__ y, int64_t len, int *__restrict__ flag)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x)
+        if (!(y[i] == 1.0 || y[i] == -1.0)) atomicOr(flag, 1);
+}
+
+// count_b = number of j with cur[b][j] != prev[b][j]; then prev = cur
+__global__ void __launch_bounds__(256) mask_diff_kernel(const uint8_t *__restrict__ cur, uint8_t *__restrict__ prev,
+                                                        int64_t d, int *__restrict__ count)
+{
+    __shared__ int sh[256];
+    const int b = blockIdx.x;
+    int c = 0;
+    for (int64_t j = threadIdx.x; j < d; j += blockDim.x) {
+        const int64_t k = (int64_t)b * d + j;
+        c += cur[k] != prev[k];
+        prev[k] = cur[k];
+    }
+    sh[threadIdx.x] = c;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) count[b] = sh[0];
 }
 
 // out_b = x_b . y_b (both [B][n]; y_stride 0 broadcasts one vector)
@@ -80,16 +195,17 @@ __global__ void __launch_bounds__(256) lin2_kernel(const double *x, const double
     }
 }
 
-// Hd_b += lam_b d_b ; out_b = d_b . Hd_b
+// Hd_b += lam_b d_b (or diag_b * d_b when diag is given) ; out_b = d_b . Hd_b
 __global__ void __launch_bounds__(256) shift_dot_kernel(const double *__restrict__ dvec, double *__restrict__ hd,
-                                                        Coefs lam, double *__restrict__ out, int64_t n)
+                                                        Coefs lam, const double *__restrict__ diag,
+                                                        double *__restrict__ out, int64_t n)
 {
     __shared__ DD sh[256];
     const int b = blockIdx.x;
     DD s{0, 0};
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
         const int64_t j = (int64_t)b * n + i;
-        const double v = __builtin_fma(lam.c[b], dvec[j], hd[j]);
+        const double v = __builtin_fma(diag ? diag[j] : lam.c[b], dvec[j], hd[j]);
         hd[j] = v;
         dd_fma(s, dvec[j], v);
     }
@@ -185,7 +301,8 @@ __device__ __forceinline__ double block_sum256(double v, double *sh4)
 // curvature along the search direction, or after max_it steps; x_b = 0 and
 // steps_b = 0 for inactive problems (act_b = 0).
 __global__ void __launch_bounds__(256) cg_dense_kernel(const double *__restrict__ J, const double *__restrict__ P,
-                                                       const double *__restrict__ grad, Coefs lam, Coefs eta,
+                                                       const double *__restrict__ grad, Coefs lam,
+                                                       const double *__restrict__ diag, Coefs eta,
                                                        Coefs act, int n, int max_it, double *__restrict__ x,
                                                        int *__restrict__ steps)
 {
@@ -202,7 +319,8 @@ __global__ void __launch_bounds__(256) cg_dense_kernel(const double *__restrict_
         if (i == 0) steps[b] = 0;
         return;
     }
-    const double lb = lam.c[b];
+    // the operator's diagonal shift: lam_b, or diag_b[i] (logistic loss)
+    const double lb = diag ? (in ? diag[(int64_t)b * n + i] : 0.0) : lam.c[b];
     auto matvec = [&](const double *M, double v) -> double {   // (M v)_i, v_i given per thread
         __syncthreads();   // sv free
         sv[i] = in ? v : 0.0;
@@ -256,12 +374,83 @@ __global__ void __launch_bounds__(256) poly3_kernel(const double *__restrict__ g
     }
 }
 
+// Streaming read of `words` 16-byte words (instrumentation: the achievable
+// HBM read rate of this device, measured beside the kernels that stream the
+// packed tensor).  Each thread keeps eight independent non-temporal loads in
+// flight; an integer sum of the loaded words per workgroup keeps them live.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) stream_read_kernel(const u32x4 *__restrict__ src, int64_t words,
+                                                          uint64_t *__restrict__ sink)
+{
+    __shared__ uint64_t sh[256];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t acc = 0;
+    for (; i + 7 * stride < words; i += 8 * stride) {
+        u32x4 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = __builtin_nontemporal_load(src + i + u * stride);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += (uint64_t)(v[u].x ^ v[u].y) + (uint64_t)(v[u].z ^ v[u].w);
+    }
+    for (; i < words; i += stride) {
+        const u32x4 a = src[i];
+        acc += (uint64_t)(a.x ^ a.y ^ a.z ^ a.w);
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sink[blockIdx.x] = sh[0];
+}
+
 }  // namespace
 
-hipError_t vec_grad(const double *g, const double *alpha, const double *y, const Coefs &lam,
-                    double *grad, double *stats, int64_t B, int64_t n, hipStream_t st)
+hipError_t probe_stream_read(const void *src, int64_t words, uint64_t *sink, int groups, hipStream_t st)
 {
-    hipLaunchKernelGGL(grad_kernel, dim3((unsigned)B), dim3(256), 0, st, g, alpha, y, lam, grad, stats, n);
+    hipLaunchKernelGGL(stream_read_kernel, dim3((unsigned)groups), dim3(256), 0, st,
+                       reinterpret_cast<const u32x4 *>(src), words, sink);
+    return hipGetLastError();
+}
+
+hipError_t vec_grad(const double *g, const double *alpha, const double *y, const Coefs &lam,
+                    double *grad, double *stats, int64_t B, int64_t n, hipStream_t st, int64_t y_stride)
+{
+    hipLaunchKernelGGL(grad_kernel, dim3((unsigned)B), dim3(256), 0, st, g, alpha, y, y_stride, lam, grad, stats, n);
+    return hipGetLastError();
+}
+hipError_t vec_grad_logistic(const double *g, const double *alpha, const double *y, int64_t y_stride,
+                             const Coefs &lam, double *grad, double *hdiag, double *stats, int64_t B, int64_t n,
+                             hipStream_t st)
+{
+    hipLaunchKernelGGL(grad_logistic_kernel, dim3((unsigned)B), dim3(256), 0, st, g, alpha, y, y_stride, lam, grad,
+                       hdiag, stats, n);
+    return hipGetLastError();
+}
+hipError_t vec_step_cap(const double *alpha, const double *x, const double *y, int64_t y_stride, const Coefs &lam,
+                        double *out, int64_t B, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(step_cap_kernel, dim3((unsigned)B), dim3(256), 0, st, alpha, x, y, y_stride, lam, out, n);
+    return hipGetLastError();
+}
+hipError_t vec_logistic_start(const double *y, int64_t y_stride, const Coefs &lam, double *alpha, int64_t B,
+                              int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(logistic_start_kernel, dim3(grid_for(n) > 8 ? 8 : grid_for(n), (unsigned)B), dim3(256), 0, st,
+                       y, y_stride, lam, alpha, n);
+    return hipGetLastError();
+}
+hipError_t vec_check_labels(const double *y, int64_t len, int *flag, hipStream_t st)
+{
+    hipLaunchKernelGGL(labels_kernel, dim3(grid_for(len)), dim3(256), 0, st, y, len, flag);
+    return hipGetLastError();
+}
+hipError_t vec_mask_diff(const uint8_t *cur, uint8_t *prev, int64_t B, int64_t d, int *count, hipStream_t st)
+{
+    hipLaunchKernelGGL(mask_diff_kernel, dim3((unsigned)B), dim3(256), 0, st, cur, prev, d, count);
     return hipGetLastError();
 }
 hipError_t vec_dot(const double *x, const double *y, int64_t y_stride, double *out, int64_t B, int64_t n,
@@ -278,9 +467,9 @@ hipError_t vec_lin2(const double *x, const double *y, const Coefs &a, const Coef
     return hipGetLastError();
 }
 hipError_t vec_shift_dot(const double *d, double *hd, const Coefs &lam, double *out, int64_t B, int64_t n,
-                         hipStream_t st)
+                         hipStream_t st, const double *diag)
 {
-    hipLaunchKernelGGL(shift_dot_kernel, dim3((unsigned)B), dim3(256), 0, st, d, hd, lam, out, n);
+    hipLaunchKernelGGL(shift_dot_kernel, dim3((unsigned)B), dim3(256), 0, st, d, hd, lam, diag, out, n);
     return hipGetLastError();
 }
 hipError_t vec_cg_update(double *x, double *r, const double *d, const double *hd, const Coefs &a, double *out,
@@ -312,11 +501,12 @@ hipError_t vec_symv(const double *A, const double *x, double *z, int64_t B, int6
 }
 
 hipError_t vec_cg_dense(const double *J, const double *P, const double *grad, const Coefs &lam, const Coefs &eta,
-                        const Coefs &act, int64_t B, int64_t n, int max_it, double *x, int *steps, hipStream_t st)
+                        const Coefs &act, int64_t B, int64_t n, int max_it, double *x, int *steps, hipStream_t st,
+                        const double *diag)
 {
     if (n > 256) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(cg_dense_kernel, dim3((unsigned)B), dim3(256), 0, st, J, P, grad, lam, eta, act, (int)n, max_it,
-                       x, steps);
+    hipLaunchKernelGGL(cg_dense_kernel, dim3((unsigned)B), dim3(256), 0, st, J, P, grad, lam, diag, eta, act, (int)n,
+                       max_it, x, steps);
     return hipGetLastError();
 }
 

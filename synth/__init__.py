@@ -14,7 +14,9 @@ from .generators import (  # noqa: F401
     CONFIGS,
     Workload,
     lambda_grid,
+    landmark_draws,
     make_workload,
+    planted_classification,
     planted_regression,
     random_alpha,
     random_symmetric_packed_values,

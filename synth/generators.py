@@ -113,6 +113,30 @@ def make_workload(name: str, *, n: Optional[int] = None, d: Optional[int] = None
     return wl
 
 
+def landmark_draws(n_total: int, ell: int, draws: int, seed: int) -> np.ndarray:
+    """``draws`` independent uniform draws of ``ell`` distinct indices out of
+    ``n_total`` (sorted within a draw), int64 [draws, ell]: the random
+    subsamples of Section 6.1, drawn here and handed to both sides."""
+    rng = np.random.default_rng(seed)
+    return np.stack([np.sort(rng.choice(n_total, size=ell, replace=False)) for _ in range(draws)]).astype(np.int64)
+
+
+def planted_classification(rng: np.random.Generator, n: int, d: int, s: int, flip: float = 0.0):
+    """Labels y = sign(X w*) in {-1, +1} for the planted-weight model above,
+    with a fraction ``flip`` of them flipped at random."""
+    X = rng.standard_normal((n, d))
+    support = np.sort(rng.choice(d, size=s, replace=False))
+    w = np.zeros(d)
+    h = rng.standard_normal(s)
+    u = rng.random(s)
+    w[support] = np.sign(h) * (1.0 - 0.3 * u)
+    y = np.sign(X @ w)
+    y[y == 0] = 1.0
+    flips = rng.random(n) < flip
+    y[flips] = -y[flips]
+    return np.ascontiguousarray(X), y, w, support
+
+
 def random_alpha(n: int, seed: int, batch: Optional[int] = None, scale: float = 1.0) -> np.ndarray:
     """Seeded N(0, scale^2) dual vectors, shape [n] or [batch, n]."""
     rng = np.random.default_rng(seed)

@@ -171,7 +171,49 @@ def test_autotuned_tiles(acc, hv):
             assert np.max(np.abs(res[b] - ref)) <= tol * np.max(np.abs(ref)), (acc, hv, tile, b)
 
 
-@pytest.mark.parametrize("n,m", [(7, 4), (70, 4), (130, 4), (5, 6), (40, 6), (9, 2)])
+@pytest.mark.parametrize("n", [200, 256])
+def test_full_size_fp64_passes_element_by_element(n):
+    """The FP64 passes of the benchmark shape (m = 4, n in (192, 256]: the
+    fourth 64-column block present) against the oracle, element by element, on
+    a random symmetric tensor: the plain and compensated contraction (one
+    vector, and a tile of 4 through the autotuner, whose returned results come
+    from the largest tile it times), and the plain directional derivative in
+    the solver's line-search form (alpha := the Newton direction x, v := the
+    iterate, with g), one vector and a tile of 2."""
+    m = 4
+    K = random_symmetric_packed_values(L.packed_count(n, m), seed=n + 5)
+    X4 = random_alpha(n, seed=n + 6, batch=4)
+    Kd, _ = _packed_dev(K, n, m)
+    x, a = X4[0], X4[1]
+    ref = [T.contract_packed(K, n, m, X4[b]) for b in range(4)]
+    E = [abs_terms(K, n, m, X4[b]) for b in range(4)]
+    depth = L.packed_count(n, m - 1) + 4 * n + 64
+    for acc in (tk.ACC_F64, tk.ACC_COMPENSATED):
+        g = to_np(tk.contract(Kd, to_dev(x), acc=acc))
+        assert np.all(np.abs(g - ref[0]) <= 2 * depth * U64 * E[0]), acc
+        np.testing.assert_allclose(g, ref[0], rtol=1e-10, atol=1e-12 * E[0].max())
+    tile, _, out = tk.autotune(Kd, to_dev(X4), acc=tk.ACC_F64)
+    out = to_np(out)
+    for b in range(4):
+        assert np.all(np.abs(out[b] - ref[b]) <= 2 * depth * U64 * E[b]), b
+    # line-search form: h = 3 K x^2 a, g = K x^3
+    h, g = tk.hvp(Kd, to_dev(x), to_dev(a), with_g=True, acc=tk.ACC_F64)
+    h, g = to_np(h), to_np(g)
+    ref_h = T.hvp_packed(K, n, m, x, a)
+    Eh = T.hvp_packed(np.abs(K), n, m, np.abs(x), np.abs(a))
+    assert np.all(np.abs(h - ref_h) <= 2 * depth * U64 * Eh)
+    assert np.all(np.abs(g - ref[0]) <= 2 * depth * U64 * E[0])
+    np.testing.assert_allclose(h, ref_h, rtol=1e-9, atol=1e-11 * Eh.max())
+    V2 = np.stack([a, X4[2]])
+    _, _, out = tk.autotune(Kd, to_dev(X4[:2]), to_dev(V2), acc=tk.ACC_F64)
+    out = to_np(out)
+    ref_h1 = T.hvp_packed(K, n, m, X4[1], X4[2])
+    Eh1 = T.hvp_packed(np.abs(K), n, m, np.abs(X4[1]), np.abs(X4[2]))
+    assert np.all(np.abs(out[0] - ref_h) <= 2 * depth * U64 * Eh)
+    assert np.all(np.abs(out[1] - ref_h1) <= 2 * depth * U64 * Eh1)
+
+
+@pytest.mark.parametrize("n,m", [(7, 4), (70, 4), (130, 4), (5, 6), (40, 6), (66, 6), (9, 2)])
 def test_hvp_f64_random_tensor(n, m):
     K = random_symmetric_packed_values(L.packed_count(n, m), seed=n * m + 1)
     B = 2

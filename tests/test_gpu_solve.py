@@ -169,3 +169,129 @@ def test_solve_zero_targets(m):
         assert not to_np(alpha).any()
         for inf in infos:
             assert inf["status"] == 0 and inf["newton_iters"] == 0, inf
+
+
+def _abs_terms_predict(X, a, Xq, m, kernel, kparam):
+    """Sum of the absolute values of the terms of f (every term made
+    nonnegative): |k| <= linear(|X|, |Xq|)^s for the linear and polynomial
+    kernels, and exp is positive."""
+    if kernel == "exp":
+        return D.predict_kernel(X, np.abs(a), Xq, m, "exp")
+    return D.predict_kernel(np.abs(X), np.abs(a), np.abs(Xq), m, kernel, kparam)
+
+
+@pytest.mark.parametrize("kernel,kparam", [("linear", 0.0), ("poly", 2), ("poly", 3), ("exp", 0.0)])
+@pytest.mark.parametrize("n,m,N", [(12, 4, 70), (30, 2, 65), (7, 6, 9), (1, 4, 3)])
+def test_predict_general_kernel_matches_oracle(kernel, kparam, n, m, N):
+    """General-kernel prediction through the C ABI against the oracle's
+    expansion over sorted (m-1)-tuples: several tuple tiles and a ragged query
+    tile; held to 1e-12 of the sum of the absolute values of the terms."""
+    rng = np.random.default_rng(100 + n + m)
+    d = 5
+    X = 0.5 * rng.standard_normal((n, d))
+    Xq = 0.5 * rng.standard_normal((N, d))
+    A = random_alpha(n, seed=7 + m, batch=3)
+    f = to_np(tk.predict_kernel(to_dev(X), to_dev(A), to_dev(Xq), m, kernel, kparam))
+    assert f.shape == (3, N)
+    for b in range(3):
+        ref = D.predict_kernel(X, A[b], Xq, m, kernel, kparam)
+        E = _abs_terms_predict(X, A[b], Xq, m, kernel, kparam)
+        assert np.all(np.abs(f[b] - ref) <= 1e-12 * E + 1e-300), (b, np.max(np.abs(f[b] - ref) / E))
+
+
+@pytest.mark.parametrize("kernel,kparam", [("poly", 2), ("exp", 0.0)])
+def test_predict_at_training_points_is_the_contraction(kernel, kparam):
+    """At a training point x_a the prediction is (K . alpha^{m-1})_a: the
+    general prediction and the packed contraction agree."""
+    rng = np.random.default_rng(5)
+    n, d, m = 70, 6, 4
+    X = 0.4 * rng.standard_normal((n, d))
+    a = random_alpha(n, seed=6)
+    Xd = to_dev(X)
+    K = tk.build_packed_tensor(Xd, m, kernel=kernel, kparam=kparam)
+    g = to_np(tk.contract(K, to_dev(a), acc=tk.ACC_COMPENSATED))
+    f = to_np(tk.predict_kernel(Xd, to_dev(a), Xd, m, kernel, kparam))
+    # both kernels are nonnegative here (even degree, exp), so the oracle's
+    # contraction of the tensor with |alpha| is the sum of |terms|
+    E = T.contract_packed(T.build_packed(X, m, kernel, kparam), n, m, np.abs(a))
+    assert np.all(np.abs(f - g) <= 1e-12 * E)
+
+
+def test_predict_general_batch_above_chunk():
+    """More vectors than one launch carries (16): chunked over the batch; the
+    linear kernel equals <w_b, x> with w_b = (X^T alpha_b)^{m-1}."""
+    rng = np.random.default_rng(12)
+    n, d, m, N = 40, 7, 4, 33
+    X = rng.standard_normal((n, d))
+    Xq = rng.standard_normal((N, d))
+    A = random_alpha(n, seed=13, batch=21)
+    f = to_np(tk.predict_kernel(to_dev(X), to_dev(A), to_dev(Xq), m))
+    for b in range(21):
+        ref = D.predict_linear(D.primal_from_dual(X, A[b], m), Xq)
+        E = np.abs(Xq) @ ((np.abs(X).T @ np.abs(A[b])) ** (m - 1))
+        assert np.all(np.abs(f[b] - ref) <= 1e-12 * E)
+
+
+@pytest.mark.parametrize("kernel,kparam,lam", [("poly", 2, 0.1), ("exp", 0.0, 0.1), ("poly", 2, 1e-2)])
+def test_solve_general_kernel_matches_oracle(kernel, kparam, lam):
+    """Dual solve on a polynomial (degree 2, as used in Section 6.2) and on an
+    exponential tensor kernel against the oracle's damped Newton on the packed
+    tensor, then prediction on held-out points with each side's alpha."""
+    rng = np.random.default_rng(31)
+    n, d, m = 24, 6, 4
+    X = 0.5 * rng.standard_normal((n + 30, d))
+    w = np.zeros(d)
+    w[[1, 4]] = [1.0, -0.7]
+    y = X @ w + 0.05 * rng.standard_normal(n + 30)
+    Xt, yt, Xq = X[:n], y[:n], X[n:]
+    K_or = T.build_packed(Xt, m, kernel, kparam)
+    c, j = D.packed_callbacks(K_or, n, m)
+    ref, info = D.solve_dual_newton(c, j, yt, lam, m)
+    K = tk.build_packed_tensor(to_dev(Xt), m, kernel=kernel, kparam=kparam)
+    alpha, infos = tk.solve_dual(K, to_dev(yt), [lam], tol=1e-11)
+    assert infos[0]["status"] == 0, infos
+    a = to_np(alpha[0])
+    assert np.linalg.norm(a - ref) <= 1e-8 * np.linalg.norm(ref), np.linalg.norm(a - ref) / np.linalg.norm(ref)
+    f = to_np(tk.predict_kernel(to_dev(Xt), alpha[0], to_dev(Xq), m, kernel, kparam))
+    f_ref = D.predict_kernel(Xt, ref, Xq, m, kernel, kparam)
+    E = _abs_terms_predict(Xt, ref, Xq, m, kernel, kparam)
+    assert np.all(np.abs(f - f_ref) <= 1e-7 * E)
+
+
+def test_nonfinite_inputs_are_rejected():
+    """tk_solve_dual and tk_dmse_dlambda check their inputs and return TK_ENAN
+    (-6) before any pass."""
+    rng = np.random.default_rng(2)
+    n, d, m = 20, 5, 4
+    X = rng.standard_normal((n, d))
+    y = rng.standard_normal(n)
+    K = tk.build_packed_tensor(to_dev(X), m)
+    for bad in (np.nan, np.inf):
+        yb = y.copy()
+        yb[7] = bad
+        with pytest.raises(tk.api._lib.TkError) as ei:
+            tk.solve_dual(K, to_dev(yb), [0.1], raise_on_noconv=True)
+        assert ei.value.code == -6
+        a0 = np.zeros(n)
+        a0[3] = bad
+        with pytest.raises(tk.api._lib.TkError) as ei:
+            tk.solve_dual(K, to_dev(y), [0.1], alpha0=to_dev(a0[None, :]), raise_on_noconv=True)
+        assert ei.value.code == -6
+        Xv = rng.standard_normal((30, d))
+        yv = rng.standard_normal(30)
+        yv[0] = bad
+        with pytest.raises(tk.api._lib.TkError) as ei:
+            tk.dmse_dlambda(K, to_dev(X), to_dev(np.ones(n)), 0.1, to_dev(Xv), to_dev(yv))
+        assert ei.value.code == -6
+
+
+def test_dmse_dlambda_reports_unconverged_cg():
+    """A CG limit below what the system needs is reported as TK_ENOCONV (-5)."""
+    rng = np.random.default_rng(8)
+    X, y, w, _ = planted_regression(rng, 40, 10, 3, 0.05, n_extra=200)
+    Xt, yt, Xv, yv = X[:40], y[:40], X[40:], y[40:]
+    a, _ = D.solve_linear(Xt, yt, 0.05, 4)
+    K = tk.build_packed_tensor(to_dev(Xt), 4)
+    with pytest.raises(tk.api._lib.TkError) as ei:
+        tk.dmse_dlambda(K, to_dev(Xt), to_dev(a), 0.05, to_dev(Xv), to_dev(yv), cg_tol=1e-14, max_cg=2)
+    assert ei.value.code == -5

@@ -152,6 +152,45 @@ def test_prediction_general_equals_primal_linear():
         np.testing.assert_allclose(f_k, f_w, rtol=1e-12)
 
 
+@pytest.mark.parametrize("kernel,kparam", [("poly", 2), ("poly", 3), ("exp", 0.0), ("linear", 0.0)])
+@pytest.mark.parametrize("m", [2, 4])
+def test_prediction_general_kernel_bruteforce(kernel, kparam, m):
+    """General-feature-map prediction (Section 4, after eq. tensor_1):
+    f(x) = sum over ordered (m-1)-tuples of k(x_{i_1}, .., x_{i_{m-1}}, x)
+    alpha_{i_1} .. alpha_{i_{m-1}}.  Pinned against the full tensor of the
+    training and query points together (einsum of the linear kernel, then the
+    polynomial power or the exponential), and at training points against the
+    contraction (f(x_a) = (K alpha^{m-1})_a)."""
+    rng = np.random.default_rng(40 + m)
+    n, d, N = 5, 3, 4
+    X = 0.6 * rng.standard_normal((n, d))
+    Xq = 0.6 * rng.standard_normal((N, d))
+    a = random_alpha(n, 41 + m)
+    Z = np.vstack([X, Xq])
+    lin = T.full_tensor_linear(Z, m)
+    F = lin ** int(kparam) if kernel == "poly" else (np.exp(lin) if kernel == "exp" else lin)
+    ref = np.empty(N)
+    for q in range(N):
+        sl = F[(slice(0, n),) * (m - 1) + (n + q,)]
+        ref[q] = float(T.contract_full(sl, a) @ a) if m > 2 else float(sl @ a)
+    got = D.predict_kernel(X, a, Xq, m, kernel, kparam)
+    np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-14 * np.abs(ref).max())
+    # at the training points the prediction is the gradient map K . alpha^{m-1}
+    g_full = T.contract_full(F[(slice(0, n),) * m], a)
+    np.testing.assert_allclose(D.predict_kernel(X, a, X, m, kernel, kparam), g_full, rtol=1e-12,
+                               atol=1e-14 * np.abs(g_full).max())
+    # a plausible mistake (every sorted tuple counted once, no multiplicity)
+    # must be caught by the brute-force pin
+    if m > 2:
+        from itertools import combinations_with_replacement
+        wrong = np.zeros(N)
+        for t in combinations_with_replacement(range(n), m - 1):
+            c = float(np.prod(a[list(t)]))
+            for q in range(N):
+                wrong[q] += c * F[tuple(t) + (n + q,)]
+        assert not np.allclose(wrong, ref, rtol=1e-6)
+
+
 def test_mse_definition():
     assert D.mse([1.0, 2.0, 4.0], [1.0, 1.0, 1.0]) == pytest.approx((0 + 1 + 9) / 3)
 
@@ -201,12 +240,42 @@ def test_bf16_rounding_pins():
     f, e = np.frexp(y)
     assert np.all(f * 256 == np.round(f * 256))
     assert np.all(np.abs(y - x) <= 2.0 ** (e - 9) + 0.0)
-    np.testing.assert_array_equal(P.round_fp32(x), x.astype(np.float32).astype(np.float64))
     # the vectorised form follows the scalar definition exactly, including ties,
     # subnormals and overflow
     z = np.concatenate([x, [1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 2.0 ** -134, 2.0 ** -133, 3 * 2.0 ** -135,
                             (2 - 2 ** -8) * 2.0 ** 127, -0.0, 0.0, np.inf, -np.inf]])
     np.testing.assert_array_equal(P.round_bf16(z), np.array([P.round_bf16_scalar(v) for v in z]))
+
+
+def test_fp32_rounding_pins():
+    """Round-to-nearest-even to FP32 (24 significant bits, exponent range
+    [-126, 127], subnormal quantum 2^-149), checked on cases whose answer
+    follows from that definition alone: exact ties, values just off a tie,
+    the subnormal range and the overflow threshold."""
+    r = lambda v: float(P.round_fp32(np.array([v]))[0])
+    assert r(1.0) == 1.0
+    assert r(1.0 + 2 ** -24) == 1.0                          # tie -> even significand
+    assert r(1.0 + 3 * 2 ** -24) == 1.0 + 2 ** -22           # tie -> even (...10)
+    assert r(1.0 + 2 ** -24 + 2 ** -40) == 1.0 + 2 ** -23    # just above the tie
+    assert r(-(1.0 + 2 ** -23)) == -(1.0 + 2 ** -23)         # representable, sign kept
+    assert r(3.0 * 2 ** 100) == 3.0 * 2 ** 100
+    assert r(2.0 ** -149) == 2.0 ** -149                     # smallest subnormal
+    assert r(2.0 ** -150) == 0.0                             # tie between 0 and 2^-149 -> 0
+    assert r(3 * 2.0 ** -150) == 2.0 ** -148                 # tie between 1 and 2 quanta -> 2
+    assert r(2.0 ** -150 + 2.0 ** -160) == 2.0 ** -149       # just above the tie
+    assert r(5 * 2.0 ** -151) == 2.0 ** -149                 # 1.25 quanta -> 1
+    assert r(2.0 ** -126) == 2.0 ** -126                     # smallest normal
+    big = (2 - 2 ** -23) * 2.0 ** 127                        # largest finite FP32
+    assert r(big) == big
+    assert r((2 - 2 ** -24) * 2.0 ** 127) == np.inf          # tie above the largest -> 2^128
+    assert r((2 - 2 ** -23 + 2 ** -30) * 2.0 ** 127) == big  # below that tie
+    assert r(-0.0) == 0.0 and np.signbit(P.round_fp32(np.array([-0.0]))[0])
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(2000) * 10.0 ** rng.integers(-30, 30, 2000)
+    y = P.round_fp32(x)
+    f, e = np.frexp(y)
+    assert np.all(f * 2 ** 24 == np.round(f * 2 ** 24))      # 24 significant bits
+    assert np.all(np.abs(y - x) <= 2.0 ** (e - 25))          # within half a unit in the last place
 
 
 def test_exact_gradient_and_refinement():
