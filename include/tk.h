@@ -122,6 +122,27 @@ int tk_contract(const void *d_K, int dtype, int64_t n, int m, const double *d_al
                 int64_t B, double *d_g, int acc, void *d_work, size_t work_bytes, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * contraction as tk_contract, with the same kernels, launch shapes and results,
+ * but no caller workspace.  Its workspace and the work plans of its passes live
+ * in a fixed device array of the library (64 MiB per device, held from the
+ * first call on that device until the process ends); the plans are copied
+ * there from host memory on every call.  The call performs no device
+ * allocation or free and records no timing events.  Calls whose workspace
+ * exceeds tk_contract_noalloc_max_bytes() (compare tk_contract_workspace for
+ * the shape) fail with TK_ENOMEM and a message, before any device work.  Every call on one device shares that device's array: calls that
+ * overlap in time on one device (different streams, or host threads) race and
+ * must be serialised by the caller; consecutive calls on one stream are safe.
+ * The array keeps the last call's contents; no kernel of the contraction
+ * reads workspace it has not written in the same call.
+ * Errors: as tk_contract, TK_ENOMEM (above the maximum).
+ */
+int tk_contract_noalloc(const void *d_K, int dtype, int64_t n, int m, const double *d_alpha,
+                        int64_t B, double *d_g, int acc, void *stream);
+size_t tk_contract_noalloc_max_bytes(void);
+
+/*
  * Directional derivative of the contraction (the adjoint of Section 4's
  * gradient map; its Jacobian is symmetric so the VJP equals the JVP):
  *   h_b = (m-1) K x_2 v_b x_3 alpha_b .. x_m alpha_b.

@@ -70,6 +70,8 @@ _SIGNATURES = {
     "tk_build_packed_tensor": (c_int, [c_vp, c_i64, c_i64, c_int, c_int, c_dbl, c_int, c_vp, c_vp]),
     "tk_contract_workspace": (c_int, [c_i64, c_int, c_i64, c_int, ctypes.POINTER(c_sz)]),
     "tk_contract": (c_int, [c_vp, c_int, c_i64, c_int, c_vp, c_i64, c_vp, c_int, c_vp, c_sz, c_vp]),
+    "tk_contract_noalloc": (c_int, [c_vp, c_int, c_i64, c_int, c_vp, c_i64, c_vp, c_int, c_vp]),
+    "tk_contract_noalloc_max_bytes": (c_sz, []),
     "tk_hvp": (c_int, [c_vp, c_int, c_i64, c_int, c_vp, c_vp, c_i64, c_vp, c_vp, c_int, c_vp, c_sz, c_vp]),
     "tk_hessian_workspace": (c_int, [c_i64, c_int, ctypes.POINTER(c_sz)]),
     "tk_hessian": (c_int, [c_vp, c_int, c_i64, c_int, c_vp, c_vp, c_vp, c_sz, c_vp]),

@@ -118,6 +118,22 @@ def contract(K: PackedTensor, alpha: torch.Tensor, acc: int = ACC_AUTO,
     return g.reshape(alpha.shape)
 
 
+def contract_noalloc(K: PackedTensor, alpha: torch.Tensor, acc: int = ACC_AUTO,
+                     out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """g = K . alpha^{m-1} through the allocation-free entry point (its
+    workspace is the library's fixed device scratch).  `out` may be given so
+    the call itself allocates nothing."""
+    alpha = _dev_f64(alpha, "alpha")
+    a2 = alpha.reshape(-1, K.n)
+    B = a2.shape[0]
+    g = torch.empty_like(a2) if out is None else out
+    if B == 0:
+        return g.reshape(alpha.shape)
+    _lib.check(_lib.load().tk_contract_noalloc(_ptr(K.data), K.dtype, K.n, K.m, _ptr(a2), B, _ptr(g), acc,
+                                               _stream()))
+    return g.reshape(alpha.shape)
+
+
 def hvp(K: PackedTensor, alpha: torch.Tensor, v: torch.Tensor, with_g: bool = False,
         work: Optional[torch.Tensor] = None, acc: int = ACC_AUTO):
     """h = (m-1) K x_2 v x_3 alpha .. x_m alpha (and g when with_g)."""

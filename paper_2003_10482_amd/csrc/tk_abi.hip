@@ -408,6 +408,76 @@ int tk_build_packed_tensor(const double *d_X, int64_t n, int64_t d, int m, int k
     return TK_OK;
 }
 
+}  // extern "C"
+
+// ------------------------------------------- allocation-free contraction ----
+// Device scratch of tk_contract_noalloc: the work plans of the passes (first
+// kScratchPlanBytes) and the contraction workspace (the rest).  Every device
+// the library runs on holds its own copy until the process ends.  In host
+// code `scratch` only names the symbol: its address on the current device
+// comes from hipGetSymbolAddress (scratch_address) and is the only form
+// passed to copies and kernels.
+namespace tk {
+namespace {
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr size_t kScratchPlanBytes = (size_t)1 << 20;
+}  // namespace
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, unsigned char *> g_scratch_addr;
+
+// Address of `scratch` on the current device, looked up once per device.
+int scratch_address(unsigned char **out)
+{
+    int dev = 0;
+    TK_HIP_CHECK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_addr.find(dev);
+    if (it == g_scratch_addr.end()) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(TK_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+        it = g_scratch_addr.emplace(dev, reinterpret_cast<unsigned char *>(p)).first;
+    }
+    *out = it->second;
+    return TK_OK;
+}
+}  // namespace
+}  // namespace tk
+
+extern "C" {
+
+size_t tk_contract_noalloc_max_bytes(void) { return kScratchBytes - kScratchPlanBytes; }
+
+int tk_contract_noalloc(const void *d_K, int dtype, int64_t n, int m, const double *d_alpha, int64_t B,
+                        double *d_g, int acc, void *stream)
+{
+    int rc;
+    if ((rc = check_nm(n, m))) return rc;
+    if ((rc = check_dtype(dtype))) return rc;
+    if (B < 1 || B > 65535) return fail(TK_EINVAL, "B must be in [1, 65535]");
+    if (!d_K || !d_alpha || !d_g) return fail(TK_EINVAL, "null device pointer");
+    int mode;
+    if ((rc = mode_for(dtype, acc, false, &mode))) return rc;
+    const ContractPlan pl = make_plan(n, m, B, mode, false, dtype);
+    const size_t cap = kScratchBytes - kScratchPlanBytes;
+    if (pl.bytes > cap)
+        return fail(TK_ENOMEM,
+                    "n = %lld, m = %d, B = %lld needs %zu bytes of scratch; the allocation-free entry point holds "
+                    "%zu (use tk_contract with a caller workspace)",
+                    (long long)n, m, (long long)B, pl.bytes, cap);
+    if (plan_area_bytes(pl) > kScratchPlanBytes)
+        return fail(TK_ENOMEM, "work plans need %zu bytes, above the %zu reserved", plan_area_bytes(pl),
+                    kScratchPlanBytes);
+    unsigned char *base = nullptr;
+    if ((rc = scratch_address(&base))) return rc;
+    const PlanArea area{base, kScratchPlanBytes};
+    return run_contract(d_K, dtype, n, m, d_alpha, nullptr, B, d_g, nullptr, mode, base + kScratchPlanBytes, cap,
+                        as_stream(stream), 0, &area);
+}
+
 int tk_contract_workspace(int64_t n, int m, int64_t B, int dtype, size_t *h_bytes)
 {
     int rc;
