@@ -113,7 +113,11 @@ int tk_contract_workspace(int64_t n, int m, int64_t B, int dtype, size_t *h_byte
  * (the gradient of the first term of eq. dual_tensor_kernel).  The packed
  * array d_K (dtype) is streamed once per tile of vectors: a workgroup applies
  * each entry it loads to a tile of 1, 2 or 4 vectors (tk_autotune picks the
- * tile), so a batch of B vectors reads K ceil(B / tile) times.  alpha and g
+ * tile), so a batch of B vectors reads K ceil(B / tile) times.  Plain FP64
+ * accumulation of an FP64 tensor with m >= 4 and n <= 256 runs the first
+ * pass, from 16 vectors on (or where tk_autotune chose it), as dense products
+ * on the FP64 matrix cores, 16 vectors per tile; the tiles of one range of K
+ * run on one XCD, so K is read from HBM about once per batch.  alpha and g
  * are FP64 [B*n].  `acc` selects the accumulation (tk_acc).  The reduction
  * order is fixed for a launch shape (see the reproducibility convention).
  * Errors: TK_EINVAL, TK_ENOMEM (work_bytes too small), TK_EUNSUPPORTED, TK_EHIP.
@@ -182,11 +186,12 @@ int tk_hessian(const void *d_K, int dtype, int64_t n, int m, const double *d_alp
  * tk_contract (d_v == NULL) or tk_hvp with B vectors and accumulation `acc`.
  * Times tiles 1, 2 and 4 (those the accumulation mode has: FP32 1/2/4, plain
  * FP64 1/2/4 for contractions and 1/2 for directional derivatives,
- * compensated 1) on this tensor and these inputs, keeps the fastest for the
- * current device and shape (later tk_contract / tk_hvp / tk_solve_dual calls
- * of that shape use it) and returns it in *h_tile.  h_ms (optional, host, 3
- * entries) receives milliseconds per call for tiles 1, 2, 4 (-1 where not
- * timed).  d_alpha, d_v: [B*n] device inputs; d_out [B*n] device scratch for
+ * compensated 1) and, for plain FP64 contractions of an FP64 tensor with
+ * m >= 4, the FP64-MFMA batch pass (tile 16, see tk_contract) on this tensor
+ * and these inputs, keeps the fastest for the current device and shape
+ * (later tk_contract / tk_hvp / tk_solve_dual calls of that shape use it) and
+ * returns it in *h_tile.  h_ms (optional, host, 4 entries) receives
+ * milliseconds per call for tiles 1, 2, 4, 16 (-1 where not timed).  d_alpha, d_v: [B*n] device inputs; d_out [B*n] device scratch for
  * the results; d_work sized by tk_contract_workspace.  Synchronises.
  * Errors: as tk_contract.
  */

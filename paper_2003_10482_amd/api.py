@@ -191,10 +191,10 @@ def autotune(K: PackedTensor, alpha: torch.Tensor, v: Optional[torch.Tensor] = N
     out = torch.empty(B, K.n, dtype=torch.float64, device=a2.device)
     work = _workspace(contract_workspace(K.n, K.m, B, K.dtype), a2.device)
     tile = ctypes.c_int()
-    ms = (ctypes.c_double * 3)()
+    ms = (ctypes.c_double * 4)()
     _lib.check(_lib.load().tk_autotune(_ptr(K.data), K.dtype, K.n, K.m, _ptr(a2), _ptr(v2), B, acc, _ptr(out),
                                        _ptr(work), work.numel(), _stream(), ctypes.byref(tile), ms))
-    return tile.value, {t: ms[i] for i, t in enumerate((1, 2, 4)) if ms[i] >= 0}, out
+    return tile.value, {t: ms[i] for i, t in enumerate((1, 2, 4, 16)) if ms[i] >= 0}, out
 
 
 LOSSES = {"square": 0, "logistic": 1}

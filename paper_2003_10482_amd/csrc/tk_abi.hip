@@ -62,6 +62,7 @@ struct PassPlan {
     int q;
     int64_t count, units;
     int groups;
+    int parts;                 // column-sum partials per vector: one per workgroup (per wave on MFMA)
     int bt;                    // vectors per tile
     size_t s_off, s_bytes;     // order q-2 output (and its tangent right after when hv)
     size_t p_off, p_bytes;     // partials (and tangent partials right after)
@@ -105,15 +106,30 @@ int tile_limit(int mode, bool hv)
     return 1;
 }
 
+// The first pass of a plain-FP64 contraction (no tangent) can run on FP64
+// MFMA, kBatchTile vectors per tile (tile id kBatchTile): by default from
+// kBatchTile vectors on, unless the autotuner chose otherwise for the shape.
+// force = kBatchTile selects it for any batch, another force a vector tile.
+bool mfma_ok(int mode, int dtype, bool hv, int64_t n, int m)
+{
+    return mode == ACC_PLAIN64 && dtype == TK_F64 && !hv && n <= 256 && m >= 4;
+}
+
 int pass_bt(int i, int mode, int64_t B, int64_t n, int m, int dtype, bool hv, int force)
 {
-    if (i != 0 || B < 2) return 1;
+    if (i != 0) return 1;
+    const bool mf = mfma_ok(mode, dtype, hv, n, m);
+    if (force == kBatchTile) return mf ? kBatchTile : 1;
+    if (B < 2) return 1;
     if (force > 0) return force < tile_limit(mode, hv) ? force : tile_limit(mode, hv);
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    std::lock_guard<std::mutex> lk(g_tile_mu);
-    auto it = g_tiles.find(TileKey{dev, dtype, mode, hv ? 1 : 0, m, n, B});
-    if (it != g_tiles.end()) return it->second;
+    {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        std::lock_guard<std::mutex> lk(g_tile_mu);
+        auto it = g_tiles.find(TileKey{dev, dtype, mode, hv ? 1 : 0, m, n, B});
+        if (it != g_tiles.end()) return it->second;
+    }
+    if (mf && B >= kBatchTile) return kBatchTile;
     return (mode == ACC_PLAIN32 && B >= 4) ? 4 : 1;
 }
 
@@ -129,14 +145,18 @@ ContractPlan make_plan(int64_t n, int m, int64_t B, int mode, bool hv, int dtype
         p.units = q >= 4 ? packed_count(n, q - 2) : 1;
         const int bt = pass_bt(i, mode, B, n, m, dtype, hv, force_bt);
         p.bt = bt;
-        p.groups = pass_groups(q, n, p.count,
-                               q >= 4 ? pass_resident(q, pass_in_kind(i, dtype, mode), mode, pass_hv(i, hv), bt, n)
-                                      : 1,
-                               (B + bt - 1) / bt);
+        if (bt == kBatchTile)
+            p.groups = batch_groups(p.units, B);
+        else
+            p.groups = pass_groups(q, n, p.count,
+                                   q >= 4 ? pass_resident(q, pass_in_kind(i, dtype, mode), mode, pass_hv(i, hv), bt, n)
+                                          : 1,
+                                   (B + bt - 1) / bt);
         p.s_bytes = q >= 4 ? align256((size_t)B * p.units * inter_size(mode)) : 0;
         p.s_off = off;
         off += p.s_bytes * (hv ? 2 : 1);
-        p.p_bytes = align256((size_t)B * p.groups * n * 2 * sizeof(double));
+        p.parts = bt == kBatchTile ? 4 * p.groups : p.groups;
+        p.p_bytes = align256((size_t)B * p.parts * n * 2 * sizeof(double));
         p.p_off = off;
         off += p.p_bytes * (hv ? 2 : 1);
     }
@@ -259,16 +279,23 @@ int run_contract(const void *K, int dtype, int64_t n, int m, const double *alpha
         const int hvl = pass_hv(i, hv);
         const int bt = pp.bt;
         TimedLaunch tl{};
-        if (i == 0 && !area)   // one read of the stored tensor(s) per tile of bt vectors
+        if (i == 0 && !area)   // one read of the stored tensor(s) per tile of bt vectors (per batch on MFMA)
             tl = timing_begin(hv ? 1 : (mode == ACC_DD ? 0 : 2),
-                              (double)pp.count * (double)dtype_size(dtype) * (double)((B + bt - 1) / bt), st);
-        hipError_t e = launch_pass(pp.q, in_kind, mode, hvl, bt, prm, pp.groups, st);
+                              (double)pp.count * (double)dtype_size(dtype) *
+                                  (double)(bt == kBatchTile ? 1 : (B + bt - 1) / bt),
+                              st);
+        hipError_t e;
+        if (bt == kBatchTile)   // a batch on FP64 MFMA: one read of K for all the vectors
+            e = launch_batch_mfma(A, pp.count, (int)n, pp.q, alpha, B, prm.plan, pp.groups, pp.units,
+                                  reinterpret_cast<double *>(prm.S_out), prm.part, st);
+        else
+            e = launch_pass(pp.q, in_kind, mode, hvl, bt, prm, pp.groups, st);
         if (e != hipSuccess) return fail(TK_EHIP, "contraction pass q=%d failed: %s", pp.q, hipGetErrorString(e));
         timing_end(tl, st);
         rv.part[i] = prm.part;
-        rv.groups[i] = pp.groups;
+        rv.groups[i] = pp.parts;
         rt.part[i] = prm.part_d;
-        rt.groups[i] = pp.groups;
+        rt.groups[i] = pp.parts;
         A = prm.S_out;
         Ad = prm.Sd_out;
         a_stride = pp.units;
@@ -298,11 +325,16 @@ size_t contract_ws(int64_t n, int m, int64_t B, int dtype)
     const int modes[3] = {dtype == TK_F64 ? ACC_DD : ACC_PLAIN32, dtype == TK_F64 ? ACC_PLAIN64 : ACC_PLAIN32,
                           ACC_PLAIN32};
     for (int mode : modes)
-        for (int hv = 0; hv < 2; ++hv)
+        for (int hv = 0; hv < 2; ++hv) {
             for (int t = 1; t <= tile_limit(mode, hv != 0); t *= 2) {
                 const size_t b = make_plan(n, m, B, mode, hv != 0, dtype, t).bytes;
                 if (b > w) w = b;
             }
+            if (mfma_ok(mode, dtype, hv != 0, n, m)) {
+                const size_t b = make_plan(n, m, B, mode, hv != 0, dtype, kBatchTile).bytes;
+                if (b > w) w = b;
+            }
+        }
     return w;
 }
 
@@ -310,10 +342,10 @@ size_t contract_ws(int64_t n, int m, int64_t B, int dtype)
 // tensor and keep the fastest for the device and shape.  alpha/vdir [B][n]
 // are timing inputs, out [B][n] receives results.  ms[t] = time of tile 2^t.
 int autotune_tile(const void *K, int dtype, int64_t n, int m, const double *alpha, const double *vdir, int64_t B,
-                  int mode, double *out, void *work, size_t work_bytes, hipStream_t st, int *tile, double ms[3])
+                  int mode, double *out, void *work, size_t work_bytes, hipStream_t st, int *tile, double ms[4])
 {
     const bool hv = vdir != nullptr;
-    for (int t = 0; t < 3; ++t) ms[t] = -1.0;
+    for (int t = 0; t < 4; ++t) ms[t] = -1.0;
     *tile = 1;
     if (B < 2) return TK_OK;
     hipEvent_t e0, e1;
@@ -324,7 +356,12 @@ int autotune_tile(const void *K, int dtype, int64_t n, int m, const double *alph
     }
     int rc = TK_OK;
     double best = INFINITY;
-    for (int t = 1, ti = 0; t <= tile_limit(mode, hv) && !rc; t *= 2, ++ti) {
+    // vector tiles 1, 2, 4 (as the mode allows), then the MFMA tile where it applies
+    int cand[4], nc = 0;
+    for (int t = 1; t <= tile_limit(mode, hv); t *= 2) cand[nc++] = t;
+    if (mfma_ok(mode, dtype, hv, n, m)) cand[nc++] = kBatchTile;
+    for (int ci = 0; ci < nc && !rc; ++ci) {
+        const int t = cand[ci], ti = t == kBatchTile ? 3 : ci;
         for (int rep = 0; rep < 3 && !rc; ++rep) {   // one untimed launch, then two timed
             if (rep == 1) hipEventRecord(e0, st);
             rc = run_contract(K, dtype, n, m, alpha, vdir, B, hv ? nullptr : out, hv ? out : nullptr, mode, work,
@@ -548,11 +585,11 @@ int tk_autotune(const void *d_K, int dtype, int64_t n, int m, const double *d_al
     const size_t need = contract_ws(n, m, B, dtype);
     if (work_bytes < need || (need && !d_work))
         return fail(TK_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", work_bytes, need);
-    double ms[3];
+    double ms[4];
     rc = autotune_tile(d_K, dtype, n, m, d_alpha, d_v, B, mode, d_out, d_work, work_bytes, as_stream(stream), h_tile,
                        ms);
     if (h_ms)
-        for (int t = 0; t < 3; ++t) h_ms[t] = ms[t];
+        for (int t = 0; t < 4; ++t) h_ms[t] = ms[t];
     return rc;
 }
 

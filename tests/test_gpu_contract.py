@@ -148,9 +148,10 @@ def test_reduced_precision_relative(n, m, storage):
 @pytest.mark.parametrize("acc", ["f64", "f32"])
 @pytest.mark.parametrize("hv", [False, True])
 def test_autotuned_tiles(acc, hv):
-    """The autotuner times the vector tiles and keeps one; the largest tile's
-    results (left in the output by the tuner) and the tuned call both match
-    the oracle (plain FP64 / FP32 accumulation bounds)."""
+    """The autotuner times the vector tiles (and, for plain FP64 contractions,
+    the MFMA batch pass) and keeps one; the last candidate's results (left in
+    the output by the tuner) and the tuned call both match the oracle (plain
+    FP64 / FP32 accumulation bounds)."""
     n, m, B = 70, 4, 6
     K = random_symmetric_packed_values(L.packed_count(n, m), seed=91 + int(hv))
     A = random_alpha(n, seed=92, batch=B)
@@ -162,7 +163,9 @@ def test_autotuned_tiles(acc, hv):
         Kd, Kr = _packed_dev(K, n, m, "f32")
         a = tk.ACC_AUTO
     tile, ms, out = tk.autotune(Kd, to_dev(A), to_dev(V) if hv else None, acc=a)
-    assert tile in ms and all(t in (1, 2, 4) for t in ms)
+    # the FP64-MFMA batch pass (tile 16) is a candidate for plain FP64 contractions only
+    assert tile in ms and set(ms) == ({1, 2, 4, 16} if (acc == "f64" and not hv) else {1, 2} if hv and acc == "f64"
+                                      else {1, 2, 4})
     got = to_np(tk.hvp(Kd, to_dev(A), to_dev(V), acc=a) if hv else tk.contract(Kd, to_dev(A), acc=a))
     for res in (to_np(out), got):
         for b in range(B):
@@ -363,3 +366,67 @@ def test_empty_batch_and_zero_vector(n, m):
         assert np.all(np.isfinite(h))
     else:
         assert not h.any()
+
+
+MFMA_SHAPES = [(1, 4), (7, 4), (15, 4), (16, 4), (17, 4), (63, 4), (64, 4), (65, 4), (70, 4), (129, 4),
+               (5, 6), (12, 6), (40, 6), (6, 8), (14, 8)]
+
+
+@pytest.mark.parametrize("n,m", MFMA_SHAPES)
+@pytest.mark.parametrize("B", [16, 17, 40])
+def test_mfma_batch_pass(n, m, B):
+    """Plain FP64 contraction of a batch of 16 or more vectors (the first pass
+    on the FP64 matrix cores, 16 vectors per tile, ragged last tile at 17 and
+    40; n across the 16-row tiles and their ragged tails) against the oracle,
+    element by element, within the same summation bound as the vector passes."""
+    count = L.packed_count(n, m)
+    K = random_symmetric_packed_values(count, seed=17 * n + m + B)
+    A = random_alpha(n, seed=n + 1000 * m + B, batch=B)
+    Kd, _ = _packed_dev(K, n, m)
+    g = to_np(tk.contract(Kd, to_dev(A), acc=tk.ACC_F64))
+    depth = L.packed_count(n, m - 1) + 4 * n + 64
+    check = range(B) if count * B < 4 * 10 ** 7 else sorted({0, 15, min(16, B - 1), B - 1})
+    for b in check:
+        ref = T.contract_packed(K, n, m, A[b])
+        E = abs_terms(K, n, m, A[b])
+        assert np.all(np.abs(g[b] - ref) <= 2 * depth * U64 * E + 1e-300), (n, m, B, b)
+
+
+def test_mfma_batch_full_size():
+    """The benchmark shape (n = 256, m = 4, C(259,4) FP64 entries) with 64
+    vectors through the MFMA batch pass: four sampled vectors (first and last
+    of the first tile, first of the second, the last) against the oracle
+    element by element; every vector against the same vector contracted alone
+    (the vector pass)."""
+    n, m, B = 256, 4, 64
+    K = random_symmetric_packed_values(L.packed_count(n, m), seed=611)
+    A = random_alpha(n, seed=612, batch=B)
+    Kd, _ = _packed_dev(K, n, m)
+    g = to_np(tk.contract(Kd, to_dev(A), acc=tk.ACC_F64))
+    depth = L.packed_count(n, m - 1) + 4 * n + 64
+    for b in (0, 15, 16, 63):
+        ref = T.contract_packed(K, n, m, A[b])
+        E = abs_terms(K, n, m, A[b])
+        assert np.all(np.abs(g[b] - ref) <= 2 * depth * U64 * E), b
+    for b in range(B):
+        one = to_np(tk.contract(Kd, to_dev(A[b]), acc=tk.ACC_F64))
+        np.testing.assert_allclose(g[b], one, rtol=1e-9, atol=1e-11 * np.abs(one).max())
+
+
+@pytest.mark.parametrize("n,m", [(129, 4), (150, 4), (192, 4), (193, 4), (70, 4), (40, 6)])
+def test_mfma_batch_reads_nothing_past_the_tensor_or_unwritten_workspace(n, m):
+    """NaN after the packed array, and NaN in the whole workspace, change no
+    result of the MFMA batch pass (B = 17: a full and a one-vector tile)."""
+    count = L.packed_count(n, m)
+    K = random_symmetric_packed_values(count, seed=5 * n + m)
+    A = to_dev(random_alpha(n, seed=n + 7, batch=17))
+    nbytes = tk.contract_workspace(n, m, 17, tk.F64)
+    res = []
+    for fill in (0.0, float("nan")):
+        buf = torch.full((count + 4096,), fill, dtype=torch.float64, device=device())
+        buf[:count] = torch.as_tensor(K, device=device())
+        Kd = tk.PackedTensor(buf[:count], n, m, tk.F64)
+        work = torch.full(((nbytes + 7) // 8,), fill, dtype=torch.float64, device=device()).view(torch.uint8)
+        res.append(to_np(tk.contract(Kd, A, acc=tk.ACC_F64, work=work)))
+    assert np.all(np.isfinite(res[1]))
+    np.testing.assert_array_equal(res[0], res[1])
