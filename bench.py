@@ -43,6 +43,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64, vector and matrix
 CSRC = os.path.join(ROOT, "paper_2003_10482_amd", "csrc")
 # timing kind -> (kernel, its source file, committed counter summary)
 KERNELS = {
@@ -56,15 +57,26 @@ KERNELS = {
                       "traffic_hess_tri_n256_m4_f64.json"),
     "hessian_units": ("hess_unit_kernel<2,double>: Hessian unit vectors", "tk_hess.hip",
                       "traffic_hess_unit_n256_m4_f64.json"),
+    # not a timing kind of its own (its launches time as contract_plain): the
+    # batch of 64 vectors in contraction_rates and counter runs
+    "contract_batch64": ("batch_mfma_kernel<2>: first pass on FP64 MFMA, 16 vectors per tile", "tk_batch.hip",
+                         "traffic_batch_mfma_n256_m4_b64_f64.json"),
 }
 
 
+def digest_sources(src: str) -> list:
+    """Files whose bytes the counter summaries of a kernel depend on: the
+    kernel's source, plus the host code that sizes its grids and plans."""
+    extra = {"tk_pass.hpp": ["tk_contract.hip", "tk_host.cpp"], "tk_hess.hip": ["tk_host.cpp"],
+             "tk_batch.hip": ["tk_host.cpp"]}
+    return [src] + extra.get(src, [])
+
+
 def source_digest(src: str) -> str:
-    """sha256 (first 16 hex digits) of the kernel's source and, for the
-    contraction passes, of the host code that sizes their grids."""
+    """sha256 (first 16 hex digits) of digest_sources(src)."""
     import hashlib
     h = hashlib.sha256()
-    for name in (src, "tk_contract.hip") if src == "tk_pass.hpp" else (src,):
+    for name in digest_sources(src):
         with open(os.path.join(CSRC, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -102,6 +114,7 @@ def pass_only(count: int, kind: str) -> int:
     g = torch.Generator(device="cpu").manual_seed(5)
     a = torch.randn(1, wl.n, generator=g, dtype=torch.float64).to(dev)
     v = torch.randn(1, wl.n, generator=g, dtype=torch.float64).to(dev)
+    a64 = torch.randn(64, wl.n, generator=g, dtype=torch.float64).to(dev)
     for _ in range(count):
         if kind == "hvp":
             tk.hvp(K, a, v)
@@ -109,6 +122,8 @@ def pass_only(count: int, kind: str) -> int:
             tk.contract(K, a, acc=tk.ACC_COMPENSATED)
         elif kind == "contract_plain":
             tk.contract(K, a, acc=tk.ACC_F64)
+        elif kind == "contract_batch64":
+            tk.contract(K, a64, acc=tk.ACC_F64)
         else:   # both Hessian kernels run in one call
             tk.hessian(K, a[0])
     src = torch.ones(2 ** 27, dtype=torch.float64, device=dev)
@@ -464,6 +479,14 @@ def contraction_rates(tk, torch, dev, X, wl, K64) -> dict:
         if vectors > 1:
             rec["vector_tile"] = tile
             rec["effective_GBs"] = vectors * K.nbytes / (avg * 1e-3) / 1e9
+            if tile == 16:   # the FP64-MFMA batch pass: 2 FMAs per entry and vector (row and column sums)
+                flops = 4.0 * K.count * vectors
+                rec["kernel"] = "batch_mfma_kernel<2>: first pass on FP64 MFMA, 16 vectors per tile"
+                rec["TFLOPs"] = flops / (avg * 1e-3) / 1e12
+                rec["frac_of_fp64_peak"] = rec["TFLOPs"] / FP64_PEAK_TFLOPS
+                t = measured_traffic("contract_batch64") if vectors == 64 else None
+                rec["traffic"] = t
+                rec["traffic_per_tensor_read"] = None if t is None else t / K.nbytes
         out[name] = rec
     return out
 

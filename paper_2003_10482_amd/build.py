@@ -17,10 +17,11 @@ OUT = os.path.join(HERE, "libtk.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 ARCH = os.environ.get("TK_OFFLOAD_ARCH", "gfx950")
 SOURCES = ["tk_pass_dd.hip", "tk_pass_f64.hip", "tk_pass_f32.hip", "tk_contract.hip", "tk_batch.hip", "tk_build.hip",
-           "tk_dense.hip", "tk_predict.hip", "tk_vec.hip", "tk_hess.hip", "tk_abi.hip"]
+           "tk_dense.hip", "tk_predict.hip", "tk_vec.hip", "tk_hess.hip", "tk_abi.hip", "tk_host.cpp"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result", "-munsafe-fp-atomics", "-ffp-contract=off"]
+HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off"]
 # Per-source additions: the batched MFMA pass adds its matrix-core results with
 # vector instructions, so its accumulators stay in VGPRs (no copies through AGPRs).
 EXTRA_FLAGS = {"tk_batch.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
@@ -50,7 +51,10 @@ def _compile(src: str, changed_only: bool = False) -> str:
     obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
     if changed_only and _up_to_date(src, obj):
         return obj
-    cmd = [hipcc(), *FLAGS, *EXTRA_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
+    if src.endswith(".cpp"):   # host-only C++ (planning, small dense algebra)
+        cmd = [shutil.which("g++") or "g++", *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    else:
+        cmd = [hipcc(), *FLAGS, *EXTRA_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")

@@ -12,6 +12,7 @@
 
 #include "tk_common.hpp"
 #include "tk_contract.hpp"
+#include "tk_host.hpp"
 #include "tk_dense.hpp"
 #include "tk_hess.hpp"
 #include "tk_vec.hpp"
@@ -66,6 +67,7 @@ struct PassPlan {
     int bt;                    // vectors per tile
     size_t s_off, s_bytes;     // order q-2 output (and its tangent right after when hv)
     size_t p_off, p_bytes;     // partials (and tangent partials right after)
+    size_t t_off;              // MFMA batch pass: the order q-2 array unit by unit, before its transpose
 };
 
 struct ContractPlan {
@@ -155,6 +157,8 @@ ContractPlan make_plan(int64_t n, int m, int64_t B, int mode, bool hv, int dtype
         p.s_bytes = q >= 4 ? align256((size_t)B * p.units * inter_size(mode)) : 0;
         p.s_off = off;
         off += p.s_bytes * (hv ? 2 : 1);
+        p.t_off = off;
+        if (bt == kBatchTile) off += p.s_bytes;
         p.parts = bt == kBatchTile ? 4 * p.groups : p.groups;
         p.p_bytes = align256((size_t)B * p.parts * n * 2 * sizeof(double));
         p.p_off = off;
@@ -287,7 +291,8 @@ int run_contract(const void *K, int dtype, int64_t n, int m, const double *alpha
         hipError_t e;
         if (bt == kBatchTile)   // a batch on FP64 MFMA: one read of K for all the vectors
             e = launch_batch_mfma(A, pp.count, (int)n, pp.q, alpha, B, prm.plan, pp.groups, pp.units,
-                                  reinterpret_cast<double *>(prm.S_out), prm.part, st);
+                                  reinterpret_cast<double *>(w + pp.t_off), reinterpret_cast<double *>(prm.S_out),
+                                  prm.part, st);
         else
             e = launch_pass(pp.q, in_kind, mode, hvl, bt, prm, pp.groups, st);
         if (e != hipSuccess) return fail(TK_EHIP, "contraction pass q=%d failed: %s", pp.q, hipGetErrorString(e));
@@ -747,59 +752,7 @@ SolveBuffers carve(void *work, int64_t n, int m, int64_t B, size_t total, int64_
     return s;
 }
 
-// a . b over [k0, k1) with four independent partial sums (the host compiler
-// may not reassociate a single chain; four chains keep its FP units busy)
-double dot4(const double *a, const double *b, int k0, int k1)
-{
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int k = k0;
-    for (; k + 3 < k1; k += 4) {
-        s0 += a[k] * b[k];
-        s1 += a[k + 1] * b[k + 1];
-        s2 += a[k + 2] * b[k + 2];
-        s3 += a[k + 3] * b[k + 3];
-    }
-    for (; k < k1; ++k) s0 += a[k] * b[k];
-    return (s0 + s1) + (s2 + s3);
-}
-
-// Inverse of a symmetric positive definite matrix (row-major, n x n) through
-// its Cholesky factor A = L L^T: W = L^{-1} by forward substitution, then
-// A^{-1} = W^T W.  Returns false when a pivot is not positive.
-bool spd_inverse(std::vector<double> &A, int n)
-{
-    std::vector<double> L((size_t)n * n, 0.0);
-    for (int j = 0; j < n; ++j) {
-        const double *Lj = &L[(size_t)j * n];
-        const double d = A[(size_t)j * n + j] - dot4(Lj, Lj, 0, j);
-        if (!(d > 0) || !std::isfinite(d)) return false;
-        const double ljj = std::sqrt(d);
-        L[(size_t)j * n + j] = ljj;
-        for (int i = j + 1; i < n; ++i) {
-            const double *Li = &L[(size_t)i * n];
-            L[(size_t)i * n + j] = (A[(size_t)i * n + j] - dot4(Li, Lj, 0, j)) / ljj;
-        }
-    }
-    // column c of W: W[c][c] = 1/L[c][c], W[i][c] = -(sum_{c<=k<i} L[i][k] W[k][c]) / L[i][i];
-    // kept transposed (Wt[c][i] = W[i][c]) so the inner sums run over contiguous memory
-    std::vector<double> Wt((size_t)n * n, 0.0);
-    for (int c = 0; c < n; ++c) {
-        double *wc = &Wt[(size_t)c * n];
-        wc[c] = 1.0 / L[(size_t)c * n + c];
-        for (int i = c + 1; i < n; ++i) {
-            const double *Li = &L[(size_t)i * n];
-            wc[i] = -dot4(Li, wc, c, i) / Li[i];
-        }
-    }
-    // (W^T W)[r][c] = sum_{k >= max(r,c)} W[k][r] W[k][c] = Wt[r] . Wt[c] over k >= max(r, c)
-    for (int r = 0; r < n; ++r)
-        for (int c = 0; c <= r; ++c) {
-            const double t = dot4(&Wt[(size_t)r * n], &Wt[(size_t)c * n], r, n);
-            A[(size_t)r * n + c] = t;
-            A[(size_t)c * n + r] = t;
-        }
-    return true;
-}
+// (dot4 and spd_inverse are in tk_host.cpp.)
 
 // Step length along a Newton direction p for an order-4 (or 2) dual: with
 // s1 = grad . p < 0, s2 = p . (J + lambda I) p, f3 = K . alpha p^3 and

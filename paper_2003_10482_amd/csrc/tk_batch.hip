@@ -40,20 +40,25 @@ namespace tk {
 namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
 constexpr int kVB = 16;       // vectors per tile (MFMA columns)
 constexpr int kXcds = 8;      // XCDs of the device: workgroup ids are dealt to them in turn
 constexpr int kXW = 70;       // row stride (doubles) of a staged chunk (16 rows x 64 columns)
-constexpr int kAS = kVB + 1;  // row stride of the alpha tile [k][v]
+// row stride of the alpha tile [k][v] with VT tiles of 16 vectors: the B
+// operand reads (16 rows x 4 k-steps per MFMA) spread over the banks
+template <int VT>
+constexpr int alpha_stride() { return VT == 1 ? kVB + 1 : 40; }
 
 struct BatchArgs {
     const double *K;
     int n;
     const double *alpha;   // [B][n]
     int64_t B;
-    int groups, tiles;
+    int groups, tiles;     // workgroup ranges per vector tile, vector tiles (of 16 VT)
+    int64_t pw;            // plan waves = column-sum partials per vector
     const int64_t *plan;   // [groups * 4 + 1]: wave w takes units [plan[w], plan[w + 1])
     int64_t units;
-    double *S_out;         // [B][units]
+    double *S_t;           // [units][B]: S unit by unit (a vector tile's 16 values share a cache line)
     double *part;          // [B][groups * 4][n] (hi, lo) pairs: one partial per wave
 };
 
@@ -186,12 +191,16 @@ struct Walk {
 // Sums of up to two of them stay below 2^32 bytes.
 constexpr int kFar = 1 << 27;
 
-template <int QP>
-__global__ void __launch_bounds__(256) batch_mfma_kernel(BatchArgs p)
+// VT tiles of 16 vectors share every staged chunk; 4 VT waves per workgroup.
+template <int QP, int VT>
+__global__ void __launch_bounds__(256 * VT) batch_mfma_kernel(BatchArgs p)
 {
-    __shared__ double as[256 * kAS];        // alpha of the tile's vectors, [k][v]
-    __shared__ double xwall[4 * 16 * kXW];  // each wave's staged chunk of M: 16 rows x 64 columns
-    __shared__ int fl[256];                 // F(l) - l, F(l) = entries of rows 0 .. l-1 of an n-wide triangle
+    constexpr int NW = 4 * VT;                 // waves per workgroup
+    constexpr int kAS = alpha_stride<VT>();
+    constexpr int NV = kVB * VT;               // vectors per workgroup
+    __shared__ double as[256 * kAS];           // alpha of the workgroup's vectors, [k][v]
+    __shared__ double xwall[NW * 16 * kXW];    // each wave's staged chunk of M: 16 rows x 64 columns
+    __shared__ int fl[256];                    // F(l) - l, F(l) = entries of rows 0 .. l-1 of an n-wide triangle
     const int n = p.n;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -203,20 +212,20 @@ __global__ void __launch_bounds__(256) batch_mfma_kernel(BatchArgs p)
     const int xcd = L % kXcds, qq = L / kXcds;
     const int tile = qq % p.tiles;
     const int group = (qq / p.tiles) * kXcds + xcd;   // < groups: the grid is groups * tiles
-    const int64_t b0 = (int64_t)tile * kVB;
+    const int64_t b0 = (int64_t)tile * NV;
     double *xw = xwall + wid * 16 * kXW;
 
-    for (int i = tid; i < 256 * kVB; i += 256) {
-        const int k = i / kVB, v = i % kVB;
+    for (int i = tid; i < 256 * NV; i += 256 * VT) {
+        const int k = i / NV, v = i % NV;
         as[k * kAS + v] = (k < n && b0 + v < p.B) ? p.alpha[(b0 + v) * n + k] : 0.0;
     }
-    fl[tid] = tid * n - tid * (tid - 1) / 2 - tid;
+    if (tid < 256) fl[tid] = tid * n - tid * (tid - 1) / 2 - tid;
     __syncthreads();   // the only workgroup barrier: alpha and the row table are read-only from here on
 
     double fq1 = 1.0;
     for (int i = 2; i <= QP + 1; ++i) fq1 *= (double)i;   // (q-1)!
-    const int64_t wave = (int64_t)group * 4 + wid;
-    const int64_t pw = (int64_t)p.groups * 4;
+    const int64_t wave = (int64_t)group * NW + wid;
+    const int64_t pw = p.pw;
     Walk<QP> cur;
     cur.start(uni64(p.plan[wave]), uni64(p.plan[wave + 1]), n);
 
@@ -274,8 +283,13 @@ __global__ void __launch_bounds__(256) batch_mfma_kernel(BatchArgs p)
         }
     };
 
-    v4d colt = v4d{0.0, 0.0, 0.0, 0.0};
-    double cu = 0.0, sacc = 0.0, sold = 0.0;
+    v4d colt[VT];
+    double cu[VT], sacc[VT], sold[VT];
+#pragma unroll
+    for (int v2 = 0; v2 < VT; ++v2) {
+        colt[v2] = v4d{0.0, 0.0, 0.0, 0.0};
+        cu[v2] = sacc[v2] = sold[v2] = 0.0;
+    }
     double wr[4], dw[4], tw[4];   // multiplicity weights of the segment being staged
     uint32_t written = 0;         // row tiles whose column sums this wave has written
     if (cur.valid) {
@@ -323,22 +337,27 @@ __global__ void __launch_bounds__(256) batch_mfma_kernel(BatchArgs p)
                 for (int q = 0; q < 4; ++q) xw[li * kXW + 16 * j + 4 * q + lk] = stg[4 * j + q];
             }
         }
-        double *sd = p.S_out + (b0 + li) * p.units + cur.u.uidx;
-        const bool s_lane = lk == 0 && b0 + li < p.B;
+        double *sd = p.S_t + cur.u.uidx * p.B + b0 + li;   // + 16 v2 for vector tile v2
         if (seg_start) {
-            // Cu for vector li; S so far (earlier row tiles of the unit), read
-            // before the next chunk's loads so that waiting for it leaves them in flight
+            // Cu for vector 16 v2 + li; S so far (earlier row tiles of the
+            // unit), read before the next chunk's loads so that waiting for it
+            // leaves them in flight
             int run = 1, wden = 1;
 #pragma unroll
             for (int i = 1; i < QP; ++i) {
                 run = (cur.u.P[i] == cur.u.P[i - 1]) ? run + 1 : 1;
                 wden *= run;
             }
-            cu = fq1 / (double)wden;
 #pragma unroll
-            for (int i = 0; i < QP; ++i) cu *= as[cur.u.P[i] * kAS + li];
-            sacc = 0.0;
-            sold = (t != ulo && s_lane) ? *sd : 0.0;
+            for (int v2 = 0; v2 < VT; ++v2) {
+                double c = fq1 / (double)wden;
+#pragma unroll
+                for (int i = 0; i < QP; ++i) c *= as[cur.u.P[i] * kAS + kVB * v2 + li];
+                cu[v2] = c;
+                sacc[v2] = 0.0;
+                const bool s_lane = lk == 0 && b0 + kVB * v2 + li < p.B;
+                sold[v2] = (t != ulo && s_lane) ? sd[kVB * v2] : 0.0;
+            }
         }
         Walk<QP> nxt = cur;
         nxt.advance(n);
@@ -346,111 +365,162 @@ __global__ void __launch_bounds__(256) batch_mfma_kernel(BatchArgs p)
             if (nxt.t != t || nxt.u.uidx != cur.u.uidx) seg_offsets(nxt);
             issue(nxt);
         }
-        // U[tile t rows, vectors] += M[tile t, chunk columns] A[chunk columns, :], four chains
-        v4d U[4] = {v4d{0.0, 0.0, 0.0, 0.0}, v4d{0.0, 0.0, 0.0, 0.0}, v4d{0.0, 0.0, 0.0, 0.0},
-                    v4d{0.0, 0.0, 0.0, 0.0}};
+        // U[tile t rows, vectors] += M[tile t, chunk columns] A[chunk columns, :]:
+        // every A operand read from LDS serves the VT vector tiles, two chains each
+        v4d U[VT][2];
+#pragma unroll
+        for (int v2 = 0; v2 < VT; ++v2) U[v2][0] = U[v2][1] = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int u = 4 * cur.c + j;
             if (u >= ulo && u < ntile) {
 #pragma unroll
-                for (int s = 0; s < 4; ++s)
-                    U[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(xw[li * kXW + 16 * j + 4 * s + lk],
-                                                                as[(16 * u + 4 * s + lk) * kAS + li], U[s], 0, 0, 0);
-            }
-        }
-        const v4d Us = (U[0] + U[1]) + (U[2] + U[3]);
-        // Cu U joins the column sums of tile t (rows 16 t + 4e + lk, vector li)
+                for (int s = 0; s < 4; ++s) {
+                    const double xa = xw[li * kXW + 16 * j + 4 * s + lk];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) colt[e] = __builtin_fma(cu, Us[e], colt[e]);
-        // S += alpha_t . U / 2 over the unit's row tiles
-#pragma unroll
-        for (int e = 0; e < 4; ++e) sacc = __builtin_fma(as[(16 * t + 4 * e + lk) * kAS + li], Us[e], sacc);
-        const bool tile_end = !nxt.valid || nxt.t != t;
-        const bool seg_end = tile_end || nxt.u.uidx != cur.u.uidx;
-        if (seg_end) {
-            double sp = sacc;
-            sp += __shfl_xor(sp, 16);
-            sp += __shfl_xor(sp, 32);
-            if (s_lane) *sd = sold + 0.5 * sp;
-        }
-        if (tile_end) {   // this wave's column sums of tile t
-            if (b0 + li < p.B) {
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int l = 16 * t + 4 * e + lk;
-                    if (l < n) {
-                        double *dst = p.part + 2 * (((b0 + li) * pw + wave) * n + l);
-                        dst[0] = colt[e];
-                        dst[1] = 0.0;
-                    }
+                    for (int v2 = 0; v2 < VT; ++v2)
+                        U[v2][s & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                            xa, as[(16 * u + 4 * s + lk) * kAS + kVB * v2 + li], U[v2][s & 1], 0, 0, 0);
                 }
             }
-            written |= 1u << t;
-            colt = v4d{0.0, 0.0, 0.0, 0.0};
         }
+        const bool tile_end = !nxt.valid || nxt.t != t;
+        const bool seg_end = tile_end || nxt.u.uidx != cur.u.uidx;
+#pragma unroll
+        for (int v2 = 0; v2 < VT; ++v2) {
+            const v4d Us = U[v2][0] + U[v2][1];
+            // Cu U joins the column sums of tile t (rows 16 t + 4e + lk, vector 16 v2 + li)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) colt[v2][e] = __builtin_fma(cu[v2], Us[e], colt[v2][e]);
+            // S += alpha_t . U / 2 over the unit's row tiles
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                sacc[v2] = __builtin_fma(as[(16 * t + 4 * e + lk) * kAS + kVB * v2 + li], Us[e], sacc[v2]);
+            if (seg_end) {
+                double sp = sacc[v2];
+                sp += __shfl_xor(sp, 16);
+                sp += __shfl_xor(sp, 32);
+                if (lk == 0 && b0 + kVB * v2 + li < p.B) sd[kVB * v2] = sold[v2] + 0.5 * sp;
+            }
+            if (tile_end) {   // this wave's column sums of tile t
+                const int64_t b = b0 + kVB * v2 + li;
+                if (b < p.B) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int l = 16 * t + 4 * e + lk;
+                        if (l < n) {
+                            double *dst = p.part + 2 * ((b * pw + wave) * n + l);
+                            *reinterpret_cast<d2 *>(dst) = d2{colt[v2][e], 0.0};
+                        }
+                    }
+                }
+                colt[v2] = v4d{0.0, 0.0, 0.0, 0.0};
+            }
+        }
+        if (tile_end) written |= 1u << t;
         seg_start = seg_end;
         cur = nxt;
     }
     // row tiles no unit of the range reaches: zero column sums
-    if (b0 + li < p.B) {
+#pragma unroll
+    for (int v2 = 0; v2 < VT; ++v2) {
+        const int64_t b = b0 + kVB * v2 + li;
+        if (b >= p.B) continue;
         for (int t = 0; t < ntile; ++t) {
             if (written & (1u << t)) continue;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int l = 16 * t + 4 * e + lk;
                 if (l < n) {
-                    double *dst = p.part + 2 * (((b0 + li) * pw + wave) * n + l);
-                    dst[0] = 0.0;
-                    dst[1] = 0.0;
+                    double *dst = p.part + 2 * ((b * pw + wave) * n + l);
+                    *reinterpret_cast<d2 *>(dst) = d2{0.0, 0.0};
                 }
             }
         }
     }
 }
 
+// S [B][units] (the next pass's per-vector arrays) from S_t [units][B]
+__global__ void __launch_bounds__(256) transpose_s_kernel(const double *S_t, double *S, int64_t units, int64_t B)
+{
+    __shared__ double tile[32][33];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int64_t u0 = (int64_t)blockIdx.x * 32, b0 = (int64_t)blockIdx.y * 32;
+    for (int r = ty; r < 32; r += 8) {
+        const int64_t u = u0 + r, b = b0 + tx;
+        tile[r][tx] = (u < units && b < B) ? S_t[u * B + b] : 0.0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int64_t b = b0 + r, u = u0 + tx;
+        if (b < B && u < units) S[b * units + u] = tile[tx][r];
+    }
+}
+
 }  // namespace
 
-// Workgroups per vector tile: about 1024 workgroups in all (two rounds of the
-// two resident per CU, so the dispatcher can even out ranges that run slower
-// than their modelled share), at most 512 and at most one per 16 units, a
-// multiple of 8 so that every XCD gets the same share of ranges.
+// Vector tiles per workgroup: two from 17 vectors on (every staged chunk then
+// feeds twice the MFMAs), one below.
+int batch_vt(int64_t B) { return B > kVB ? 2 : 1; }
+
+// Plan groups (of four waves) of the batch pass: about two rounds of
+// workgroups (two resident per CU with one vector tile, one with two), at
+// most one group per 16 units, a multiple of 8 VT so that every XCD gets the
+// same share of ranges.
 int batch_groups(int64_t units, int64_t B)
 {
-    const int64_t tiles = (B + kVB - 1) / kVB;
-    int64_t g = 1024 / (tiles < 1 ? 1 : tiles);
+    const int vt = batch_vt(B);
+    const int64_t tiles = (B + kVB * vt - 1) / (kVB * vt);
+    int64_t wg = (vt == 1 ? 1024 : 512) / (tiles < 1 ? 1 : tiles);   // workgroups per tile
+    int64_t g = wg * vt;
     const int64_t cap = (units + 15) / 16;
     if (g > cap) g = cap;
-    if (g > 512) g = 512;
-    g = (g + kXcds - 1) / kXcds * kXcds;
-    if (g < kXcds) g = kXcds;
+    if (g > 512 * vt) g = 512 * vt;
+    const int64_t step = (int64_t)kXcds * vt;
+    g = (g + step - 1) / step * step;
+    if (g < step) g = step;
     return (int)g;
 }
 
 hipError_t launch_batch_mfma(const void *K, int64_t count, int n, int q, const double *alpha, int64_t B,
-                             const int64_t *plan, int groups, int64_t units, double *S_out, double *part,
-                             hipStream_t st)
+                             const int64_t *plan, int groups, int64_t units, double *S_t, double *S_out,
+                             double *part, hipStream_t st)
 {
     (void)count;
-    if (n < 1 || n > 256 || groups < kXcds || groups % kXcds || B < 1) return hipErrorInvalidValue;
+    const int vt = batch_vt(B);
+    if (n < 1 || n > 256 || groups < kXcds * vt || groups % (kXcds * vt) || B < 1) return hipErrorInvalidValue;
     BatchArgs a{};
     a.K = reinterpret_cast<const double *>(K);
     a.n = n;
     a.alpha = alpha;
     a.B = B;
     a.groups = groups;
-    a.tiles = (int)((B + kVB - 1) / kVB);
+    a.tiles = (int)((B + kVB * vt - 1) / (kVB * vt));
     a.plan = plan;
     a.units = units;
-    a.S_out = S_out;
+    a.S_t = S_t;
     a.part = part;
-    const unsigned grid = (unsigned)groups * (unsigned)a.tiles;
-    switch (q) {
-    case 4: hipLaunchKernelGGL(batch_mfma_kernel<2>, dim3(grid), dim3(256), 0, st, a); break;
-    case 6: hipLaunchKernelGGL(batch_mfma_kernel<4>, dim3(grid), dim3(256), 0, st, a); break;
-    case 8: hipLaunchKernelGGL(batch_mfma_kernel<6>, dim3(grid), dim3(256), 0, st, a); break;
+    // workgroups: groups / vt ranges (of 4 vt waves each) times the vector tiles
+    const unsigned grid = (unsigned)(groups / vt) * (unsigned)a.tiles;
+    const dim3 blk(256 * vt);
+    // kernel argument `groups` is the plan's group count: the workgroup's
+    // range index runs to groups / vt
+    BatchArgs ak = a;
+    ak.groups = groups / vt;
+    ak.pw = (int64_t)groups * 4;
+    switch (q * 4 + vt) {
+    case 17: hipLaunchKernelGGL((batch_mfma_kernel<2, 1>), dim3(grid), blk, 0, st, ak); break;
+    case 18: hipLaunchKernelGGL((batch_mfma_kernel<2, 2>), dim3(grid), blk, 0, st, ak); break;
+    case 25: hipLaunchKernelGGL((batch_mfma_kernel<4, 1>), dim3(grid), blk, 0, st, ak); break;
+    case 26: hipLaunchKernelGGL((batch_mfma_kernel<4, 2>), dim3(grid), blk, 0, st, ak); break;
+    case 33: hipLaunchKernelGGL((batch_mfma_kernel<6, 1>), dim3(grid), blk, 0, st, ak); break;
+    case 34: hipLaunchKernelGGL((batch_mfma_kernel<6, 2>), dim3(grid), blk, 0, st, ak); break;
     default: return hipErrorInvalidValue;
     }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(transpose_s_kernel, dim3((unsigned)((units + 31) / 32), (unsigned)((B + 31) / 32)), dim3(256), 0,
+                       st, S_t, S_out, units, B);
     return hipGetLastError();
 }
 

@@ -8,6 +8,7 @@
 #include <string>
 
 #include "../../include/tk.h"
+#include "tk_limits.hpp"
 
 namespace tk {
 
@@ -23,11 +24,6 @@ int fail(int code, const char *fmt, ...);
                               __FILE__, __LINE__);                                         \
     } while (0)
 
-// Compile-time limits of the contraction kernels.
-constexpr int kWave = 64;          // CDNA wavefront width
-constexpr int kMaxBlocks = 4;      // columns per lane: n <= kWave * kMaxBlocks
-constexpr int kMaxOrder = 8;       // largest even tensor order instantiated
-constexpr int kMaxPoints = kWave * kMaxBlocks;
 
 // ------------------------------------------------------------ binomials ----
 // C(a, b) for 0 <= b <= 16; exact in int64 for every size this library accepts

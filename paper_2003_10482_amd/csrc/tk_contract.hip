@@ -10,6 +10,7 @@
 
 #include "tk_common.hpp"
 #include "tk_contract.hpp"
+#include "tk_host.hpp"
 
 namespace tk {
 
@@ -67,67 +68,8 @@ __global__ void __launch_bounds__(256) reduce_partials_kernel(ReduceParams p)
 }
 
 // ------------------------------------------------------------ work plans ----
-// Modelled cost of one row (fixed part plus one term per 64-column block it
-// touches) and of one unit (fixed part).  The weights approximate the
-// instruction counts of the kernel; only their ratios matter.
+// (make_plan_host is in tk_host.cpp.)
 namespace {
-constexpr double kCostRow = 6.0, kCostBlock = 8.0, kCostBatch = 4.0, kCostUnit = 60.0;
-
-std::vector<int64_t> make_plan_host(int q, int64_t n, int64_t waves)
-{
-    const int nb = (int)((n + kWave - 1) / kWave);
-    // cost of the rows k in [k0, n) of a unit whose leading indices end at k0
-    std::vector<double> tail(n + 1, 0.0);
-    for (int64_t k = n - 1; k >= 0; --k) tail[k] = tail[k + 1] + kCostRow + kCostBlock * (nb - (k >> 6));
-    std::vector<int64_t> plan(waves + 1, 0);
-    if (q == 2) {
-        double total = tail[0];
-        int64_t w = 1;
-        double acc = 0.0;
-        for (int64_t k = 0; k < n && w < waves; ++k) {
-            acc += kCostRow + kCostBlock * (nb - (k >> 6));
-            while (w < waves && acc >= total * (double)w / (double)waves) plan[w++] = k + 1;
-        }
-        while (w <= waves) plan[w++] = n;
-        plan[waves] = n;
-        return plan;
-    }
-    const int qp = q - 2;
-    auto unit_cost = [&](int k0) {
-        const double rows = (double)(n - k0);
-        return tail[k0] + kCostBatch * std::ceil(rows / 4.0) + kCostUnit;
-    };
-    // units in nested-loop order; only the last index matters for the cost
-    std::vector<int> t(qp, 0);
-    double total = 0.0;
-    int64_t units = 0;
-    while (true) {
-        total += unit_cost(t[qp - 1]);
-        ++units;
-        int pos = qp - 1;
-        while (pos >= 0 && t[pos] == n - 1) --pos;
-        if (pos < 0) break;
-        t[pos] += 1;
-        for (int i = pos + 1; i < qp; ++i) t[i] = t[pos];
-    }
-    std::fill(t.begin(), t.end(), 0);
-    int64_t w = 1, u = 0;
-    double acc = 0.0;
-    while (u < units && w < waves) {
-        acc += unit_cost(t[qp - 1]);
-        ++u;
-        while (w < waves && acc >= total * (double)w / (double)waves) plan[w++] = u;
-        int pos = qp - 1;
-        while (pos >= 0 && t[pos] == n - 1) --pos;
-        if (pos < 0) break;
-        t[pos] += 1;
-        for (int i = pos + 1; i < qp; ++i) t[i] = t[pos];
-    }
-    while (w <= waves) plan[w++] = units;
-    plan[waves] = units;
-    return plan;
-}
-
 std::mutex g_plan_mu;
 std::map<std::tuple<int, int, int64_t, int>, int64_t *> g_plans;
 std::mutex g_hplan_mu;

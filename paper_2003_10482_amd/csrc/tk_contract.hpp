@@ -60,12 +60,12 @@ hipError_t launch_reduce(const ReduceParams &rp, int64_t B, hipStream_t st);
 // First pass of a plain-FP64 contraction of a batch of vectors on FP64 MFMA
 // (tk_batch.hip): the outputs of the vector kernel's first pass, with one
 // partial per wave (partials [B][4 groups][n] as (hi, lo) pairs, and the
-// order q-2 array [B][units]).
+// order q-2 array [B][units], built in S_t [units][B] and transposed).
 // groups: a multiple of 8 (batch_groups(units, B)); plan: pass_plan(q, n, groups).
 constexpr int kBatchTile = 16;   // vectors per MFMA tile; batches from this size use it
 int batch_groups(int64_t units, int64_t B);
 hipError_t launch_batch_mfma(const void *K, int64_t count, int n, int q, const double *alpha, int64_t B,
-                             const int64_t *plan, int groups, int64_t units, double *S_out, double *part,
-                             hipStream_t st);
+                             const int64_t *plan, int groups, int64_t units, double *S_t, double *S_out,
+                             double *part, hipStream_t st);
 
 }  // namespace tk

@@ -31,16 +31,11 @@
 #include <vector>
 
 #include "tk_hess.hpp"
+#include "tk_host.hpp"
 
 namespace tk {
 namespace {
 
-constexpr int kHessJT = 16;                  // tile positions per lane
-constexpr int kHessL = kHessJT * kWave;      // upper-triangle entries per row tile (at most)
-constexpr int kHessItems = 4096;             // target work items of the tile kernel
-constexpr int kHessRWaves = 32768;           // target waves of the unit kernel
-constexpr int kHessXWaves = 4096;            // target waves of the cross kernel
-constexpr int kTB = kMaxOrder + 1;           // binomial table: C(a, b) for b < kTB
 
 __host__ __device__ inline int64_t tri(int64_t L) { return L * (L + 1) / 2; }
 
@@ -440,93 +435,7 @@ __global__ __launch_bounds__(256) void hess_combine(const double *__restrict__ U
 }
 
 // ------------------------------------------------------------------- plans --
-struct HostPlan {
-    std::vector<int> tiles;         // [ntiles][2]
-    std::vector<int> tile_items;    // [ntiles + 1]
-    std::vector<int64_t> items;     // [nitems][3]
-    std::vector<int64_t> rplan;     // [rwaves + 1]
-    std::vector<int64_t> tab;       // [(n + kTB) * kTB]
-    int64_t nq = 0;
-    int xs = 0;
-    int ntiles() const { return (int)tiles.size() / 2; }
-    int nitems() const { return (int)items.size() / 3; }
-    int rwaves() const { return rplan.empty() ? 0 : (int)rplan.size() - 1; }
-};
-
-HostPlan make_host_plan(int64_t n, int m)
-{
-    HostPlan h;
-    const int MP = m - 2;
-    const int nb = (int)((n + kWave - 1) / kWave);
-    // row tiles of at most kHessL upper-triangle entries
-    std::vector<int64_t> work;
-    double wtot = 0;
-    for (int k = 0; k < n;) {
-        const int k0 = k;
-        int64_t L = 0;
-        while (k < n && L + (n - k) <= kHessL) L += n - k++;
-        h.tiles.push_back(k0);
-        h.tiles.push_back(k);
-        const int64_t units = MP == 0 ? 1 : binom(k + MP - 1, MP);
-        work.push_back(units * ((L + kWave - 1) / kWave + 6));
-        wtot += (double)work.back();
-    }
-    h.tile_items.push_back(0);
-    for (int t = 0; t < h.ntiles(); ++t) {
-        const int k1 = h.tiles[2 * t + 1];
-        const int64_t units = MP == 0 ? 1 : binom(k1 + MP - 1, MP);
-        int64_t it = (int64_t)std::llround((double)work[t] / wtot * kHessItems);
-        it = std::max<int64_t>(1, std::min(it, units));
-        const int64_t chunk = (units + it - 1) / it;
-        for (int64_t u = 0; u < units; u += chunk) {
-            h.items.push_back(t);
-            h.items.push_back(u);
-            h.items.push_back(std::min(units, u + chunk));
-        }
-        h.tile_items.push_back(h.nitems());
-    }
-    h.tab.assign((size_t)(n + kTB) * kTB, 0);
-    for (int64_t a = 0; a < n + kTB; ++a)
-        for (int b = 0; b < kTB; ++b) h.tab[(size_t)a * kTB + b] = binom(a, b);
-    if (MP >= 2) {
-        // unit plan balanced on modelled cost: per batch of 8 rows, the
-        // loads of the column blocks it touches plus the reduction
-        std::vector<double> cost_d(n);
-        for (int d = 0; d < n; ++d) {
-            double c = 16.0;
-            for (int kb = d; kb < n; kb += 8) c += 8.0 * (nb - (kb >> 6)) + 12.0;
-            cost_d[d] = c;
-        }
-        const int64_t units = binom(n + MP - 1, MP);
-        double total = 0;   // units ending in d: C(d + MP - 1, MP - 1)
-        for (int d = 0; d < n; ++d) total += cost_d[d] * (double)binom(d + MP - 1, MP - 1);
-        const int64_t waves = std::max<int64_t>(1, std::min<int64_t>(kHessRWaves, units));
-        h.rplan.push_back(0);
-        std::vector<int> P(MP, 0);
-        double cum = 0;
-        int64_t w = 1;
-        for (int64_t u = 0; u < units && w < waves; ++u) {
-            // cut before unit u once the units before it reach the next share
-            if (cum >= total * (double)w / (double)waves && u > h.rplan.back()) {
-                h.rplan.push_back(u);
-                ++w;
-            }
-            cum += cost_d[P[MP - 1]];
-            int p = MP - 1;
-            while (p >= 0 && P[p] + 1 >= n) --p;
-            if (p >= 0) {
-                const int v = P[p] + 1;
-                for (int q = p; q < MP; ++q) P[q] = v;
-            }
-        }
-        h.rplan.push_back(units);
-        h.nq = binom(n + MP - 2, MP - 1);
-        const int64_t xs = (kHessXWaves + n - 1) / n;
-        h.xs = (int)std::max<int64_t>(1, std::min<int64_t>(xs, h.nq));
-    }
-    return h;
-}
-
+// (HostPlan and make_host_plan are in tk_host.cpp.)
 std::mutex g_hess_mu;
 std::map<std::tuple<int64_t, int>, HostPlan> g_host_plans;
 
