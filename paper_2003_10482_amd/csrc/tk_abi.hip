@@ -787,6 +787,23 @@ double quartic_step(double s1, double s2, double f3, double f4)
 // Device slot b of the preconditioner holds an inverse (J' + lambda' I)^{-1}
 // from an earlier iterate (and, along a lambda path, an earlier lambda): a
 // stale inverse still preconditions the current system well.
+// Pinned host staging for the solver's small readbacks (per host thread,
+// grown as needed and kept until the process ends): copies into it need no
+// pageable bounce.  Every readback is synchronised before the next use.
+void *pinned_stage(size_t bytes)
+{
+    thread_local void *p = nullptr;
+    thread_local size_t cap = 0;
+    if (bytes > cap) {
+        void *q = nullptr;
+        if (hipHostMalloc(&q, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+        if (p) (void)hipHostFree(p);
+        p = q;
+        cap = bytes;
+    }
+    return p;
+}
+
 struct Precond {
     bool dev = false;
     bool ident = false;   // ... and that inverse is I / lambda' (from J = 0 at alpha = 0)
@@ -795,7 +812,7 @@ struct Precond {
     // lambda, so it carries along a path
     bool have_J = false;
     double moved = 0.0;
-    double jnorm = 0.0;   // Frobenius norm of the last J factored on the host (>= ||J||_2)
+    double jnorm = 0.0;   // Frobenius norm of the last J inverted (>= ||J||_2)
 };
 
 struct ProblemState {
@@ -851,8 +868,11 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
     const int refresh = o.precond_refresh > 0 ? o.precond_refresh : 8;
 
     auto sync_copy = [&](double *dst, const double *src, size_t cnt) -> int {
-        TK_HIP_CHECK(hipMemcpyAsync(dst, src, cnt * sizeof(double), hipMemcpyDeviceToHost, st));
+        void *pin = pinned_stage(cnt * sizeof(double));
+        if (!pin) return fail(TK_EHIP, "pinned host buffer allocation failed");
+        TK_HIP_CHECK(hipMemcpyAsync(pin, src, cnt * sizeof(double), hipMemcpyDeviceToHost, st));
         TK_HIP_CHECK(hipStreamSynchronize(st));
+        std::memcpy(dst, pin, cnt * sizeof(double));
         return TK_OK;
     };
     // On FP64 storage, from a cold start (alpha = 0), the gradient passes use
@@ -908,11 +928,60 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
         hess_passes += hp;
         return TK_OK;
     };
-    // (J_b + lambda I)^{-1} (J_b + diag(h_b) for the logistic loss) into the
-    // device preconditioner slot b, factored on the host (Cholesky); a rounded
-    // J may miss positive definiteness by its rounding: shift more.  J = 0
-    // gives I / lambda directly.
+    // (J_b + lambda I)^{-1} (J_b + diag(h_b) for the logistic loss) by
+    // Newton-Schulz on the device, X <- 2 X - X A X with the dense MFMA
+    // products: three steps from the previous inverse (J has moved little),
+    // else forty from I / ||A||_F; kept when ||I - A X||_F < 1/4 (one
+    // synchronisation).  ok = 0 leaves it to the host factorisation.
+    auto refresh_inverse_device = [&](int64_t b, int &ok) -> int {
+        ok = 0;
+        if (n < 2 || sb.cw_bytes < 2 * (size_t)n * n * sizeof(double)) return TK_OK;
+        double *X = sb.P + b * n * n;
+        const double *J = sb.Jd + b * n * n;
+        double *T = reinterpret_cast<double *>(sb.cw);
+        double *XT = T + n * n;
+        const double *dg = logistic ? sb.hdiag + b * n : nullptr;
+        const double lb = ps[b].lam;
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            const bool warm = attempt == 0;
+            if (warm && !(pc[b].dev && !pc[b].ident)) continue;   // no previous inverse
+            if (!warm) TK_HIP_CHECK(ns_init(J, lb, dg, X, n, st));
+            const int iters = warm ? 3 : 40;
+            for (int k = 0; k < iters; ++k) {
+                TK_HIP_CHECK(launch_gemm(J, n, X, n, 1, T, n, n, n, n, 1, st));   // T = A X
+                TK_HIP_CHECK(ns_shift(T, X, lb, dg, n, st));
+                TK_HIP_CHECK(launch_gemm(X, n, T, n, 1, XT, n, n, n, n, 1, st));  // XT = X A X
+                TK_HIP_CHECK(ns_update(X, XT, n, st));
+            }
+            TK_HIP_CHECK(ns_symmetrize(X, n, st));
+            TK_HIP_CHECK(launch_gemm(J, n, X, n, 1, T, n, n, n, n, 1, st));
+            TK_HIP_CHECK(ns_shift(T, X, lb, dg, n, st));
+            TK_HIP_CHECK(ns_residual(T, J, n, XT, st));
+            double out[2];
+            TK_HIP_CHECK(hipMemcpyAsync(out, XT, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+            TK_HIP_CHECK(hipStreamSynchronize(st));
+            if (std::isfinite(out[0]) && out[0] < 0.25) {
+                pc[b].jnorm = out[1];
+                ok = 1;
+                return TK_OK;
+            }
+        }
+        return TK_OK;
+    };
+    // The same on the host (Cholesky), when Newton-Schulz does not settle: a
+    // rounded J may miss positive definiteness by its rounding: shift more.
+    // J = 0 gives I / lambda directly.
     auto refresh_inverse = [&](int64_t b, bool zero) -> int {
+        if (!zero) {
+            int ok = 0;
+            if (int rc2 = refresh_inverse_device(b, ok)) return rc2;
+            if (ok) {
+                pc_updates[b]++;
+                pc[b].dev = true;
+                pc[b].ident = false;
+                return TK_OK;
+            }
+        }
         std::vector<double> A((size_t)n * n, 0.0);
         std::vector<double> hdg;
         if (zero) {
@@ -1131,6 +1200,7 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
             for (int64_t b = 0; b < B; ++b) act.c[b] = ps[b].done ? 0.0 : 1.0;
             const int max_cg = o.max_cg > 0 ? o.max_cg : 2000;
             std::vector<int> cg_steps(B, 0);
+            bool cg_pending = false;
             std::vector<double> eta(B);
             for (int64_t b = 0; b < B; ++b) eta[b] = std::min(0.5, std::max(std::sqrt(ps[b].gn / gn0[b]), 1e-12));
             if (use_pc) {
@@ -1141,10 +1211,7 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                 int *dsteps = reinterpret_cast<int *>(sb.stats2);
                 TK_HIP_CHECK(vec_cg_dense(sb.Jd, sb.P, sb.grad, lam, etac, act, B, n, max_cg, sb.x, dsteps, st,
                                           logistic ? sb.hdiag : nullptr));
-                TK_HIP_CHECK(hipMemcpyAsync(cg_steps.data(), dsteps, B * sizeof(int), hipMemcpyDeviceToHost, st));
-                TK_HIP_CHECK(hipStreamSynchronize(st));
-                for (int64_t b = 0; b < B; ++b)
-                    if (!ps[b].done) ps[b].cg += cg_steps[b];
+                cg_pending = true;   // the step counts come back with the line statistics below
             } else {
                 // unpreconditioned, every product one directional-derivative pass over the tensor
                 std::vector<double> rz(B);
@@ -1193,37 +1260,107 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                     TK_HIP_CHECK(vec_lin2(sb.r, sb.dv, keep, beta, sb.dv, B, n, st));   // d = r + beta d
                 }
             }
-            for (int64_t b = 0; b < B; ++b)
-                if (!ps[b].done) ps[b].last_cg = cg_steps[b];
-            // if CG produced nothing (zero curvature at the first step), fall back to steepest descent
-            TK_HIP_CHECK(vec_dot(sb.x, sb.x, n, sb.stats, B, n, st));
-            if ((rc = sync_copy(hr.data(), sb.stats, B))) return rc;
-            {
-                Coefs c1{}, c2{};
-                for (int64_t b = 0; b < B; ++b) {
-                    c1.c[b] = 1.0;
-                    if (!ps[b].done && !(hr[b] > 0)) {
-                        c1.c[b] = 0.0;
-                        c2.c[b] = -1.0 / std::max(ps[b].lam, 1e-300);
-                    }
-                }
-                TK_HIP_CHECK(vec_lin2(sb.x, sb.grad, c1, c2, sb.x, B, n, st));
-            }
-            std::vector<double> xnorm(B);
-            for (int64_t b = 0; b < B; ++b) xnorm[b] = hr[b] > 0 ? std::sqrt(hr[b]) : INFINITY;
-            // slope = grad . x
-            TK_HIP_CHECK(vec_dot(sb.grad, sb.x, n, sb.stats, B, n, st));
-            std::vector<double> slope(B), t(B, 1.0);
-            if ((rc = sync_copy(slope.data(), sb.stats, B))) return rc;
+            // ---- the line along x: ||x||^2, the slope grad . x and, for the
+            // exact step, the model of D along x, all read back in one copy
+            // with the CG step counts (statistics slices: model [0, 3B),
+            // x.x [3B, 4B), grad.x [4B, 5B))
             bool need_model = false;   // the model pass is skipped once every problem takes unit steps
             for (int64_t b = 0; b < B; ++b)
                 if (!ps[b].done && !(std::fabs(last_t[b] - 1.0) <= 0.05)) need_model = true;
+            const bool model = !logistic && use_pc && (m == 2 || m == 4) && need_model;
             // m = 4 on FP64 storage with plain gradients and J fresh at alpha:
             // the contraction along the line is the cubic
             //   K (alpha + t x)^3 = g + t J x + t^2 (3 K x^2 alpha) + t^3 K x^3,
             // so one directional-derivative pass at x along alpha (which also
             // returns K x^3) replaces the gradient passes of the line search
             bool algebraic = false;
+            std::vector<double> mod(3 * B, 0.0);
+            // s2 from the assembled Hessian, and for m = 4 the cubic and quartic
+            // terms from one pass giving dv = K . x^3 (D is a quartic in the step)
+            auto enqueue_model = [&]() -> int {
+                algebraic = m == 4 && dt == TK_F64 && !accurate && !o.polish_K;
+                for (int64_t b = 0; b < B; ++b)
+                    if (!ps[b].done && !jfresh[b]) algebraic = false;
+                TK_HIP_CHECK(vec_symv(sb.Jd, sb.x, sb.z, B, n, st));                 // z = J x
+                TK_HIP_CHECK(vec_lin2(sb.z, sb.z, one, zero, sb.hd, B, n, st));
+                TK_HIP_CHECK(vec_shift_dot(sb.x, sb.hd, lam, sb.stats, B, n, st));
+                if (m == 4) {
+                    int rc2;
+                    if (algebraic) {   // r = 3 K x^2 alpha, dv = K x^3
+                        if ((rc2 = run_contract(Kp, dt, n, m, sb.x, alpha, B, sb.dv, sb.r, ACC_PLAIN64, sb.cw,
+                                                sb.cw_bytes, st, 0, nullptr, cx.k_stride)))
+                            return rc2;
+                    } else {
+                        const int pm = dt == TK_F64 ? ACC_PLAIN64 : ACC_PLAIN32;
+                        if ((rc2 = run_contract(Kp, dt, n, m, sb.x, nullptr, B, sb.dv, nullptr, pm, sb.cw,
+                                                sb.cw_bytes, st, 0, nullptr, cx.k_stride)))
+                            return rc2;
+                    }
+                    passes++;
+                    TK_HIP_CHECK(vec_dot(alpha, sb.dv, n, sb.stats + B, B, n, st));
+                    TK_HIP_CHECK(vec_dot(sb.x, sb.dv, n, sb.stats + 2 * B, B, n, st));
+                }
+                return TK_OK;
+            };
+            std::vector<double> hr0(B), slope(B), t(B, 1.0);
+            {
+                TK_HIP_CHECK(vec_dot(sb.x, sb.x, n, sb.stats + 3 * B, B, n, st));
+                TK_HIP_CHECK(vec_dot(sb.grad, sb.x, n, sb.stats + 4 * B, B, n, st));
+                if (model && (rc = enqueue_model())) return rc;
+                unsigned char *pin = reinterpret_cast<unsigned char *>(pinned_stage(5 * B * sizeof(double) + B * sizeof(int)));
+                if (!pin) return fail(TK_EHIP, "pinned host buffer allocation failed");
+                TK_HIP_CHECK(hipMemcpyAsync(pin, sb.stats, 5 * B * sizeof(double), hipMemcpyDeviceToHost, st));
+                if (cg_pending)
+                    TK_HIP_CHECK(hipMemcpyAsync(pin + 5 * B * sizeof(double), sb.stats2, B * sizeof(int),
+                                                hipMemcpyDeviceToHost, st));
+                TK_HIP_CHECK(hipStreamSynchronize(st));
+                const double *pd = reinterpret_cast<const double *>(pin);
+                for (int64_t b = 0; b < B; ++b) {
+                    mod[b] = pd[b];
+                    mod[B + b] = pd[B + b];
+                    mod[2 * B + b] = pd[2 * B + b];
+                    hr0[b] = pd[3 * B + b];
+                    slope[b] = pd[4 * B + b];
+                }
+                if (cg_pending) {
+                    std::memcpy(cg_steps.data(), pin + 5 * B * sizeof(double), B * sizeof(int));
+                    for (int64_t b = 0; b < B; ++b)
+                        if (!ps[b].done) ps[b].cg += cg_steps[b];
+                }
+            }
+            for (int64_t b = 0; b < B; ++b)
+                if (!ps[b].done) ps[b].last_cg = cg_steps[b];
+            // if CG produced nothing (zero curvature at the first step), fall back
+            // to steepest descent; the slope and model are then taken again
+            bool fallback = false;
+            {
+                Coefs c1{}, c2{};
+                for (int64_t b = 0; b < B; ++b) {
+                    c1.c[b] = 1.0;
+                    if (!ps[b].done && !(hr0[b] > 0)) {
+                        c1.c[b] = 0.0;
+                        c2.c[b] = -1.0 / std::max(ps[b].lam, 1e-300);
+                        fallback = true;
+                    }
+                }
+                if (fallback) {
+                    TK_HIP_CHECK(vec_lin2(sb.x, sb.grad, c1, c2, sb.x, B, n, st));
+                    TK_HIP_CHECK(vec_dot(sb.grad, sb.x, n, sb.stats + 4 * B, B, n, st));
+                    if (model && (rc = enqueue_model())) return rc;
+                    std::vector<double> all(5 * B);
+                    if ((rc = sync_copy(all.data(), sb.stats, 5 * B))) return rc;
+                    for (int64_t b = 0; b < B; ++b) {
+                        if (model) {
+                            mod[b] = all[b];
+                            mod[B + b] = all[B + b];
+                            mod[2 * B + b] = all[2 * B + b];
+                        }
+                        slope[b] = all[4 * B + b];
+                    }
+                }
+            }
+            std::vector<double> xnorm(B);
+            for (int64_t b = 0; b < B; ++b) xnorm[b] = hr0[b] > 0 ? std::sqrt(hr0[b]) : INFINITY;
             if (logistic) {
                 // the separable term is not a polynomial: start the backtracking
                 // at the full step, shortened to stay inside the domain
@@ -1232,37 +1369,7 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                 if ((rc = sync_copy(cap.data(), sb.stats, B))) return rc;
                 for (int64_t b = 0; b < B; ++b)
                     if (!ps[b].done) t[b] = std::min(1.0, 0.99 * cap[b]);
-            } else if (use_pc && (m == 2 || m == 4) && need_model) {
-                // exact model of D along x: s2 from the assembled Hessian, and
-                // for m = 4 the cubic and quartic terms from one pass giving
-                // dv = K . x^3 (D is a quartic polynomial in the step length)
-                algebraic = m == 4 && dt == TK_F64 && !accurate && !o.polish_K;
-                for (int64_t b = 0; b < B; ++b)
-                    if (!ps[b].done && !jfresh[b]) algebraic = false;
-                // s2, f3, f4 land in three slices of the statistics buffer and
-                // reach the host in one copy
-                std::vector<double> mod(3 * B, 0.0);
-                TK_HIP_CHECK(vec_symv(sb.Jd, sb.x, sb.z, B, n, st));                 // z = J x
-                TK_HIP_CHECK(vec_lin2(sb.z, sb.z, one, zero, sb.hd, B, n, st));
-                TK_HIP_CHECK(vec_shift_dot(sb.x, sb.hd, lam, sb.stats, B, n, st));
-                if (m == 4) {
-                    if (algebraic) {   // r = 3 K x^2 alpha, dv = K x^3
-                        if ((rc = run_contract(Kp, dt, n, m, sb.x, alpha, B, sb.dv, sb.r, ACC_PLAIN64, sb.cw,
-                                               sb.cw_bytes, st, 0, nullptr, cx.k_stride)))
-                            return rc;
-                    } else {
-                        const int pm = dt == TK_F64 ? ACC_PLAIN64 : ACC_PLAIN32;
-                        if ((rc = run_contract(Kp, dt, n, m, sb.x, nullptr, B, sb.dv, nullptr, pm, sb.cw, sb.cw_bytes,
-                                               st, 0, nullptr, cx.k_stride)))
-                            return rc;
-                    }
-                    passes++;
-                    TK_HIP_CHECK(vec_dot(alpha, sb.dv, n, sb.stats + B, B, n, st));
-                    TK_HIP_CHECK(vec_dot(sb.x, sb.dv, n, sb.stats + 2 * B, B, n, st));
-                    if ((rc = sync_copy(mod.data(), sb.stats, 3 * B))) return rc;
-                } else if ((rc = sync_copy(mod.data(), sb.stats, B))) {
-                    return rc;
-                }
+            } else if (model) {
                 for (int64_t b = 0; b < B; ++b)
                     if (!ps[b].done) t[b] = quartic_step(slope[b], mod[b], mod[B + b], mod[2 * B + b]);
             }

@@ -2,6 +2,8 @@
 // reduction is a fixed tree with compensated (double-double) partial sums, so
 // the solver's scalars are reproducible and accurate to about 2^-100.
 #include "tk_common.hpp"
+#include <algorithm>
+
 #include "tk_vec.hpp"
 
 namespace tk {
@@ -380,6 +382,85 @@ __global__ void __launch_bounds__(256) poly3_kernel(const double *__restrict__ g
 // flight; an integer sum of the loaded words per workgroup keeps them live.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
+// ---- Newton-Schulz inverse of a dense SPD matrix (preconditioner refresh)
+// One workgroup sums n^2 entries in a fixed order: per-thread strided
+// partial sums, then a tree over the 256 threads.
+__device__ double block_sum_256(double v, double *sh)
+{
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(256) ns_init_kernel(const double *__restrict__ J, double lam,
+                                                      const double *__restrict__ diag, double *__restrict__ X, int n)
+{
+    __shared__ double sh[256];
+    double f = 0.0;
+    for (int64_t k = threadIdx.x; k < (int64_t)n * n; k += 256) {
+        const int i = (int)(k / n), j = (int)(k % n);
+        const double a = J[k] + (i == j ? (diag ? diag[i] : lam) : 0.0);
+        f = __builtin_fma(a, a, f);
+    }
+    const double fro = sqrt(block_sum_256(f, sh));
+    const double s = fro > 0.0 ? 1.0 / fro : 0.0;
+    for (int64_t k = threadIdx.x; k < (int64_t)n * n; k += 256) X[k] = (k / n == k % n) ? s : 0.0;
+}
+
+__global__ void __launch_bounds__(256) ns_shift_kernel(double *__restrict__ T, const double *__restrict__ X, double lam,
+                                                       const double *__restrict__ diag, int n)
+{
+    const int64_t nn = (int64_t)n * n;
+    for (int64_t k = blockIdx.x * 256 + threadIdx.x; k < nn; k += (int64_t)gridDim.x * 256) {
+        const double d = diag ? diag[k / n] : lam;
+        T[k] = __builtin_fma(d, X[k], T[k]);
+    }
+}
+
+__global__ void __launch_bounds__(256) ns_update_kernel(double *__restrict__ X, const double *__restrict__ XT, int n)
+{
+    const int64_t nn = (int64_t)n * n;
+    for (int64_t k = blockIdx.x * 256 + threadIdx.x; k < nn; k += (int64_t)gridDim.x * 256)
+        X[k] = 2.0 * X[k] - XT[k];
+}
+
+__global__ void __launch_bounds__(256) ns_residual_kernel(const double *__restrict__ T, const double *__restrict__ J,
+                                                          int n, double *__restrict__ out)
+{
+    __shared__ double sh[256];
+    double r = 0.0, f = 0.0;
+    for (int64_t k = threadIdx.x; k < (int64_t)n * n; k += 256) {
+        const double e = (k / n == k % n ? 1.0 : 0.0) - T[k];
+        r = __builtin_fma(e, e, r);
+        f = __builtin_fma(J[k], J[k], f);
+    }
+    const double rs = block_sum_256(r, sh);
+    const double fs = block_sum_256(f, sh);
+    if (threadIdx.x == 0) {
+        out[0] = sqrt(rs);
+        out[1] = sqrt(fs);
+    }
+}
+
+__global__ void __launch_bounds__(256) ns_symmetrize_kernel(double *__restrict__ X, int n)
+{
+    // the thread of entry (i, j), j > i, averages the pair and writes both
+    const int64_t nn = (int64_t)n * n;
+    for (int64_t k = blockIdx.x * 256 + threadIdx.x; k < nn; k += (int64_t)gridDim.x * 256) {
+        const int i = (int)(k / n), j = (int)(k % n);
+        if (j <= i) continue;
+        const double v = 0.5 * (X[k] + X[(int64_t)j * n + i]);
+        X[k] = v;
+        X[(int64_t)j * n + i] = v;
+    }
+}
+
 __global__ void __launch_bounds__(256) stream_read_kernel(const u32x4 *__restrict__ src, int64_t words,
                                                           uint64_t *__restrict__ sink)
 {
@@ -515,6 +596,40 @@ hipError_t vec_poly3(const double *g, const double *a, const double *c, const do
 {
     hipLaunchKernelGGL(poly3_kernel, dim3(grid_for(n) > 8 ? 8 : grid_for(n), (unsigned)B), dim3(256), 0, st, g, a, c,
                        e, t, z, n);
+    return hipGetLastError();
+}
+
+hipError_t ns_init(const double *J, double lam, const double *diag, double *X, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(ns_init_kernel, dim3(1), dim3(256), 0, st, J, lam, diag, X, (int)n);
+    return hipGetLastError();
+}
+
+hipError_t ns_shift(double *T, const double *X, double lam, const double *diag, int64_t n, hipStream_t st)
+{
+    const unsigned g = (unsigned)std::min<int64_t>(256, (n * n + 255) / 256);
+    hipLaunchKernelGGL(ns_shift_kernel, dim3(g), dim3(256), 0, st, T, X, lam, diag, (int)n);
+    return hipGetLastError();
+}
+
+hipError_t ns_update(double *X, const double *XT, int64_t n, hipStream_t st)
+{
+    const unsigned g = (unsigned)std::min<int64_t>(256, (n * n + 255) / 256);
+    hipLaunchKernelGGL(ns_update_kernel, dim3(g), dim3(256), 0, st, X, XT, (int)n);
+    return hipGetLastError();
+}
+
+hipError_t ns_residual(const double *T, const double *J, int64_t n, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(ns_residual_kernel, dim3(1), dim3(256), 0, st, T, J, (int)n, out);
+    return hipGetLastError();
+}
+
+hipError_t ns_symmetrize(double *X, int64_t n, hipStream_t st)
+{
+    if (n < 2) return hipSuccess;
+    const unsigned g = (unsigned)std::min<int64_t>(256, (n * n + 255) / 256);
+    hipLaunchKernelGGL(ns_symmetrize_kernel, dim3(g), dim3(256), 0, st, X, (int)n);
     return hipGetLastError();
 }
 

@@ -55,4 +55,17 @@ hipError_t probe_stream_read(const void *src, int64_t words, uint64_t *sink, int
 // z_b = A_b x_b (A_b symmetric [n][n], row-major)
 hipError_t vec_symv(const double *A, const double *x, double *z, int64_t B, int64_t n, hipStream_t st);
 
+// Newton-Schulz inverse of A = J + diag(d) (d_i = lam, or diag[i] when diag
+// is given), n x n row-major, with the dense MFMA products:
+//   ns_init:     X = I / ||A||_F (every eigenvalue of A X then lies in (0, 1])
+//   ns_shift:    T += diag(d) X   (T = J X before: T = A X)
+//   ns_update:   X = 2 X - XT     (XT = X T)
+//   ns_residual: out[0] = ||I - T||_F, out[1] = ||J||_F (fixed-order sums)
+//   ns_symmetrize: X = (X + X^T) / 2
+hipError_t ns_init(const double *J, double lam, const double *diag, double *X, int64_t n, hipStream_t st);
+hipError_t ns_shift(double *T, const double *X, double lam, const double *diag, int64_t n, hipStream_t st);
+hipError_t ns_update(double *X, const double *XT, int64_t n, hipStream_t st);
+hipError_t ns_residual(const double *T, const double *J, int64_t n, double *out, hipStream_t st);
+hipError_t ns_symmetrize(double *X, int64_t n, hipStream_t st);
+
 }  // namespace tk
