@@ -59,7 +59,7 @@ KERNELS = {
                       "traffic_hess_unit_n256_m4_f64.json"),
     # not a timing kind of its own (its launches time as contract_plain): the
     # batch of 64 vectors in contraction_rates and counter runs
-    "contract_batch64": ("batch_mfma_kernel<2>: first pass on FP64 MFMA, 16 vectors per tile", "tk_batch.hip",
+    "contract_batch64": ("batch_mfma_kernel<2,2>: first pass on FP64 MFMA, two tiles of 16 vectors", "tk_batch.hip",
                          "traffic_batch_mfma_n256_m4_b64_f64.json"),
 }
 
@@ -481,7 +481,7 @@ def contraction_rates(tk, torch, dev, X, wl, K64) -> dict:
             rec["effective_GBs"] = vectors * K.nbytes / (avg * 1e-3) / 1e9
             if tile == 16:   # the FP64-MFMA batch pass: 2 FMAs per entry and vector (row and column sums)
                 flops = 4.0 * K.count * vectors
-                rec["kernel"] = "batch_mfma_kernel<2>: first pass on FP64 MFMA, 16 vectors per tile"
+                rec["kernel"] = KERNELS["contract_batch64"][0]
                 rec["TFLOPs"] = flops / (avg * 1e-3) / 1e12
                 rec["frac_of_fp64_peak"] = rec["TFLOPs"] / FP64_PEAK_TFLOPS
                 t = measured_traffic("contract_batch64") if vectors == 64 else None
