@@ -7,7 +7,8 @@
 // to l >= P_last.  A workgroup computes a 64-row x 64-column tile: Q and X
 // chunks are staged in LDS and each wave accumulates a 32 x 32 quarter with
 // FP64 MFMA (v_mfma_f64_16x16x4f64, 2 x 2 tiles: every operand read from LDS
-// feeds 16 FMAs).  The kernel value (linear / polynomial / exponential) is
+// feeds 16 FMAs), skipping the 16 x 16 blocks that lie wholly left of the
+// rows' starts.  The kernel value (linear / polynomial / exponential) is
 // formed in FP64 and rounded once to the storage type.
 #include "tk_common.hpp"
 
@@ -58,6 +59,7 @@ __global__ void __launch_bounds__(256) build_kernel(const double *__restrict__ X
     __shared__ int64_t roff[TR];
     __shared__ int rk[TR];
     __shared__ int kmin;
+    __shared__ int kmin16[TR / 16];   // smallest row start of each group of 16 rows
 
     const int t = threadIdx.x;
     const int64_t row0 = (int64_t)blockIdx.x * TR;
@@ -83,6 +85,12 @@ __global__ void __launch_bounds__(256) build_kernel(const double *__restrict__ X
     }
     __syncthreads();
     if (kmin > c0 + TC - 1 || c0 >= n) return;   // every row starts right of this tile
+    if (t < TR / 16) {
+        int m16 = n;
+        for (int r = 16 * t; r < 16 * t + 16; ++r) m16 = rk[r] < m16 ? rk[r] : m16;
+        kmin16[t] = m16;
+    }
+    __syncthreads();
 
     // wave w owns the 32 x 32 quarter (rows 32 (w / 2), columns 32 (w % 2))
     // as 2 x 2 MFMA tiles of 16 x 16; v_mfma_f64_16x16x4f64 takes
@@ -97,6 +105,15 @@ __global__ void __launch_bounds__(256) build_kernel(const double *__restrict__ X
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    // 16 x 16 blocks whose rows all start right of their columns hold no entry
+    // of the tensor: their products are skipped (about half the tile's work
+    // near the diagonal; the decision is uniform across the wave)
+    bool need[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            need[i][j] = __builtin_amdgcn_readfirstlane(kmin16[(wr >> 4) + i]) <= c0 + wc + 16 * j + 15;
 
     for (int f0 = 0; f0 < d; f0 += FCH) {
         // stage q_P[f] for the tile rows and x_l[f] for the tile columns
@@ -123,7 +140,8 @@ __global__ void __launch_bounds__(256) build_kernel(const double *__restrict__ X
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+                for (int j = 0; j < 2; ++j)
+                    if (need[i][j]) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
         }
         __syncthreads();
     }
