@@ -259,6 +259,16 @@ def lambda_path(tk, torch, dev) -> dict:
                "newton_iters": sum(i["newton_iters"] for i in infos),
                "all_converged": all(i["status"] == 0 for i in infos),
                "support_f1_min": min(f1), "support_f1_mean": float(np.mean(f1))}
+        if tol == 1e-4:
+            # the same lambdas in lock step (every pass one launch for all 64
+            # vectors, the plain passes on the FP64-MFMA batch kernel; one
+            # Hessian per lambda and Newton step)
+            tk.solve_dual(K, y, wl.lambdas[-2:], tol=tol, continuation=False)
+            (al, il), dl = timed(lambda: tk.solve_dual(K, y, wl.lambdas, tol=tol, continuation=False))
+            fl = f1_of(al)
+            rec["lock_step"] = {"seconds": dl, "newton_iters_max": max(i["newton_iters"] for i in il),
+                                "all_converged": all(i["status"] == 0 for i in il),
+                                "support_f1_min": min(fl), "speed_vs_continuation": dt / dl}
         # the same 64 lambdas as independent cold FP64 solves: the speedup of
         # the batched form at equal support accuracy
         A, di = timed(lambda: torch.cat([tk.solve_dual(K, y, [lam], tol=tol)[0] for lam in wl.lambdas]))

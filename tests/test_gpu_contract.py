@@ -430,3 +430,25 @@ def test_mfma_batch_reads_nothing_past_the_tensor_or_unwritten_workspace(n, m):
         res.append(to_np(tk.contract(Kd, A, acc=tk.ACC_F64, work=work)))
     assert np.all(np.isfinite(res[1]))
     np.testing.assert_array_equal(res[0], res[1])
+
+
+def test_batch_reads_the_tensor_once_per_launch_by_the_library_count():
+    """A plain FP64 contraction of 64 vectors runs its pass over K once (the
+    FP64-MFMA batch pass): the library's own count of the pass's tensor bytes
+    is C x 8 for the whole batch, and results match 64 separate calls."""
+    n, m, B = 70, 4, 64
+    count = L.packed_count(n, m)
+    K = random_symmetric_packed_values(count, seed=4242)
+    Kd, _ = _packed_dev(K, n, m)
+    A = to_dev(random_alpha(n, seed=4243, batch=B))
+    tk.contract(Kd, A, acc=tk.ACC_F64)   # plans and workspace
+    torch.cuda.synchronize()
+    tk.timing_start()
+    g = tk.contract(Kd, A, acc=tk.ACC_F64)
+    torch.cuda.synchronize()
+    launches, _, nbytes = tk.timing_stop()["contract_plain"]
+    assert launches == 1 and nbytes == count * 8
+    g = to_np(g)
+    for b in (0, 31, 32, 63):
+        one = to_np(tk.contract(Kd, A[b], acc=tk.ACC_F64))
+        np.testing.assert_allclose(g[b], one, rtol=1e-10, atol=1e-12 * np.abs(one).max())
