@@ -804,6 +804,26 @@ void *pinned_stage(size_t bytes)
     return p;
 }
 
+// Wait for the work enqueued on `st` so far by polling an event: the solver
+// waits on a small readback after every few kernels, and a polling wait
+// resumes within microseconds where a blocking one can take tens.
+hipError_t spin_sync(hipStream_t st)
+{
+    thread_local hipEvent_t ev = nullptr;
+    if (!ev) {
+        hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            ev = nullptr;
+            return e;
+        }
+    }
+    hipError_t e = hipEventRecord(ev, st);
+    if (e != hipSuccess) return e;
+    while ((e = hipEventQuery(ev)) == hipErrorNotReady) {
+    }
+    return e;
+}
+
 struct Precond {
     bool dev = false;
     bool ident = false;   // ... and that inverse is I / lambda' (from J = 0 at alpha = 0)
@@ -871,7 +891,7 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
         void *pin = pinned_stage(cnt * sizeof(double));
         if (!pin) return fail(TK_EHIP, "pinned host buffer allocation failed");
         TK_HIP_CHECK(hipMemcpyAsync(pin, src, cnt * sizeof(double), hipMemcpyDeviceToHost, st));
-        TK_HIP_CHECK(hipStreamSynchronize(st));
+        TK_HIP_CHECK(spin_sync(st));
         std::memcpy(dst, pin, cnt * sizeof(double));
         return TK_OK;
     };
@@ -890,7 +910,7 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
         std::vector<double> yy(rows);
         TK_HIP_CHECK(vec_dot(y, y, cx.y_stride, sb.stats, rows, n, st));
         TK_HIP_CHECK(hipMemcpyAsync(yy.data(), sb.stats, rows * sizeof(double), hipMemcpyDeviceToHost, st));
-        TK_HIP_CHECK(hipStreamSynchronize(st));
+        TK_HIP_CHECK(spin_sync(st));
         for (double v : yy) ynorm = std::max(ynorm, std::sqrt(v));
     }
     // gradient pass at `a` into (gdst, graddst), statistics to the host
@@ -959,7 +979,7 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
             TK_HIP_CHECK(ns_residual(T, J, n, XT, st));
             double out[2];
             TK_HIP_CHECK(hipMemcpyAsync(out, XT, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-            TK_HIP_CHECK(hipStreamSynchronize(st));
+            TK_HIP_CHECK(spin_sync(st));
             if (std::isfinite(out[0]) && out[0] < 0.25) {
                 pc[b].jnorm = out[1];
                 ok = 1;
@@ -994,7 +1014,7 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                 TK_HIP_CHECK(hipMemcpyAsync(hdg.data(), sb.hdiag + b * n, n * sizeof(double), hipMemcpyDeviceToHost,
                                             st));
             }
-            TK_HIP_CHECK(hipStreamSynchronize(st));
+            TK_HIP_CHECK(spin_sync(st));
             double tr = 0.0, fro = 0.0;
             for (int64_t i = 0; i < n; ++i) tr += std::fabs(A[i * n + i]);
             for (int64_t i = 0; i < n * n; ++i) fro += A[i] * A[i];
@@ -1015,7 +1035,7 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
         }
         TK_HIP_CHECK(hipMemcpyAsync(sb.P + b * n * n, A.data(), (size_t)n * n * sizeof(double), hipMemcpyHostToDevice,
                                     st));
-        TK_HIP_CHECK(hipStreamSynchronize(st));
+        TK_HIP_CHECK(spin_sync(st));
         pc_updates[b]++;
         pc[b].dev = true;
         pc[b].ident = zero;
@@ -1102,7 +1122,7 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                 TK_HIP_CHECK(vec_mask_diff(sb.mask_cur, sb.mask_prev, B, cx.sd, sb.sup_cnt, st));
                 std::vector<int> cnt(B);
                 TK_HIP_CHECK(hipMemcpyAsync(cnt.data(), sb.sup_cnt, B * sizeof(int), hipMemcpyDeviceToHost, st));
-                TK_HIP_CHECK(hipStreamSynchronize(st));
+                TK_HIP_CHECK(spin_sync(st));
                 for (int64_t b = 0; b < B; ++b) {
                     if (ps[b].done) continue;
                     stable[b] = (it > 0 && cnt[b] == 0) ? stable[b] + 1 : 0;
@@ -1313,7 +1333,7 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                 if (cg_pending)
                     TK_HIP_CHECK(hipMemcpyAsync(pin + 5 * B * sizeof(double), sb.stats2, B * sizeof(int),
                                                 hipMemcpyDeviceToHost, st));
-                TK_HIP_CHECK(hipStreamSynchronize(st));
+                TK_HIP_CHECK(spin_sync(st));
                 const double *pd = reinterpret_cast<const double *>(pin);
                 for (int64_t b = 0; b < B; ++b) {
                     mod[b] = pd[b];

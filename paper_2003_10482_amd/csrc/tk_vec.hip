@@ -284,83 +284,102 @@ __global__ void __launch_bounds__(256) symv_kernel(const double *__restrict__ A,
     if (lane == 0) z[(int64_t)b * n + row] = s;
 }
 
-// Sum over the 256 threads of a workgroup (4 waves): shuffles, then the four
-// wave sums through LDS; every thread returns the total.
-__device__ __forceinline__ double block_sum256(double v, double *sh4)
+// Sum over the 1024 threads of a workgroup (16 waves): shuffles, then the
+// 16 wave sums through LDS in a fixed order; every thread returns the total.
+__device__ __forceinline__ double block_sum1024(double v, double *sh16)
 {
 #pragma unroll
     for (int s = 32; s >= 1; s >>= 1) v += __shfl_xor(v, s);
-    __syncthreads();   // sh4 free (previous readers done)
-    if ((threadIdx.x & 63) == 0) sh4[threadIdx.x >> 6] = v;
+    __syncthreads();   // sh16 free (previous readers done)
+    if ((threadIdx.x & 63) == 0) sh16[threadIdx.x >> 6] = v;
     __syncthreads();
-    return (sh4[0] + sh4[1]) + (sh4[2] + sh4[3]);
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) t += sh16[w];
+    return t;
 }
 
 // Preconditioned CG on (J_b + lam_b I) x = -grad_b, one problem per
-// workgroup, thread i owning component i (n <= 256); J_b and P_b symmetric
-// [n][n] (P_b the preconditioner), read by columns so the loads of a step
-// are coalesced.  Stops at ||r|| <= eta_b ||grad_b||, at non-positive
-// curvature along the search direction, or after max_it steps; x_b = 0 and
-// steps_b = 0 for inactive problems (act_b = 0).
-__global__ void __launch_bounds__(256) cg_dense_kernel(const double *__restrict__ J, const double *__restrict__ P,
-                                                       const double *__restrict__ grad, Coefs lam,
-                                                       const double *__restrict__ diag, Coefs eta,
-                                                       Coefs act, int n, int max_it, double *__restrict__ x,
-                                                       int *__restrict__ steps)
+// workgroup of 1024 threads: thread (q, i) = (t / 256, t % 256) sums the
+// products of quarter q of the columns for component i (n <= 256), so that
+// 16 waves stream each product's matrix and its dependent chains are a
+// quarter long; every thread then holds component i of the vectors.  J_b and
+// P_b symmetric [n][n] (P_b the preconditioner), read by columns so the loads
+// of a step are coalesced.  Stops at ||r|| <= eta_b ||grad_b||, at
+// non-positive curvature along the search direction, or after max_it steps;
+// x_b = 0 and steps_b = 0 for inactive problems (act_b = 0).
+__global__ void __launch_bounds__(1024) cg_dense_kernel(const double *__restrict__ J, const double *__restrict__ P,
+                                                        const double *__restrict__ grad, Coefs lam,
+                                                        const double *__restrict__ diag, Coefs eta,
+                                                        Coefs act, int n, int max_it, double *__restrict__ x,
+                                                        int *__restrict__ steps)
 {
-    __shared__ double sv[256];   // the vector of the next product (d, then r)
-    __shared__ double sh4[4];
+    __shared__ double sv[256];       // the vector of the next product (d, then r)
+    __shared__ double part[4][256];  // the quarters' partial products
+    __shared__ double sh16[16];
     const int b = blockIdx.x;
-    const int i = threadIdx.x;
+    const int t = threadIdx.x;
+    const int i = t & 255, q = t >> 8;
     const bool in = i < n;
+    const bool own = q == 0 && in;   // the thread that counts component i in the sums
     const double *Jb = J + (int64_t)b * n * n;
     const double *Pb = P + (int64_t)b * n * n;
     double *xb = x + (int64_t)b * n;
     if (!(act.c[b] > 0)) {
-        if (in) xb[i] = 0.0;
-        if (i == 0) steps[b] = 0;
+        if (own) xb[i] = 0.0;
+        if (t == 0) steps[b] = 0;
         return;
     }
+    const int qlen = (n + 3) / 4;
+    const int j0 = q * qlen, j1 = (j0 + qlen) < n ? (j0 + qlen) : n;
     // the operator's diagonal shift: lam_b, or diag_b[i] (logistic loss)
     const double lb = diag ? (in ? diag[(int64_t)b * n + i] : 0.0) : lam.c[b];
     auto matvec = [&](const double *M, double v) -> double {   // (M v)_i, v_i given per thread
-        __syncthreads();   // sv free
-        sv[i] = in ? v : 0.0;
+        __syncthreads();   // sv and part free
+        if (q == 0) sv[i] = in ? v : 0.0;
         __syncthreads();
-        double s = 0.0;
-        if (in)
-            for (int j = 0; j < n; ++j) s = __builtin_fma(M[(int64_t)j * n + i], sv[j], s);
-        return s;
+        double s0 = 0.0, s1 = 0.0;
+        if (in) {
+            int j = j0;
+            for (; j + 1 < j1; j += 2) {
+                s0 = __builtin_fma(M[(int64_t)j * n + i], sv[j], s0);
+                s1 = __builtin_fma(M[(int64_t)(j + 1) * n + i], sv[j + 1], s1);
+            }
+            if (j < j1) s0 = __builtin_fma(M[(int64_t)j * n + i], sv[j], s0);
+        }
+        part[q][i] = s0 + s1;
+        __syncthreads();
+        return (part[0][i] + part[1][i]) + (part[2][i] + part[3][i]);
     };
     const double gi = in ? grad[(int64_t)b * n + i] : 0.0;
-    const double gn = sqrt(block_sum256(gi * gi, sh4));
+    const double gn = sqrt(block_sum1024(own ? gi * gi : 0.0, sh16));
     double xi = 0.0, ri = -gi;
     double zi = matvec(Pb, ri);
-    double rz = block_sum256(ri * zi, sh4);
+    double rz = block_sum1024(own ? ri * zi : 0.0, sh16);
     double di = zi;
     int it = 0;
     if (gn > 0 && rz > 0) {
         for (; it < max_it; ++it) {
             const double hi = matvec(Jb, di) + lb * di;
-            const double dhd = block_sum256(di * hi, sh4);
+            const double dhd = block_sum1024(own ? di * hi : 0.0, sh16);
             if (!(dhd > 0) || !isfinite(dhd)) break;   // no positive curvature along d
             const double a = rz / dhd;
             xi = __builtin_fma(a, di, xi);
             ri = __builtin_fma(-a, hi, ri);
-            const double rr = block_sum256(ri * ri, sh4);
+            const double rr = block_sum1024(own ? ri * ri : 0.0, sh16);
             if (sqrt(rr) <= eta.c[b] * gn) {
                 ++it;
                 break;
             }
             zi = matvec(Pb, ri);
-            const double rzn = block_sum256(ri * zi, sh4);
+            const double rzn = block_sum1024(own ? ri * zi : 0.0, sh16);
             const double beta = rzn / rz;
             rz = rzn;
             di = __builtin_fma(beta, di, zi);
         }
     }
-    if (in) xb[i] = xi;
-    if (i == 0) steps[b] = it;
+    if (own) xb[i] = xi;
+    if (t == 0) steps[b] = it;
 }
 
 // z_b = g_b + t_b (a_b + t_b (c_b + t_b e_b)), a cubic in the step length.
@@ -586,7 +605,7 @@ hipError_t vec_cg_dense(const double *J, const double *P, const double *grad, co
                         const double *diag)
 {
     if (n > 256) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(cg_dense_kernel, dim3((unsigned)B), dim3(256), 0, st, J, P, grad, lam, diag, eta, act, (int)n,
+    hipLaunchKernelGGL(cg_dense_kernel, dim3((unsigned)B), dim3(1024), 0, st, J, P, grad, lam, diag, eta, act, (int)n,
                        max_it, x, steps);
     return hipGetLastError();
 }
