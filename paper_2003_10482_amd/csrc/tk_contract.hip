@@ -15,34 +15,38 @@
 namespace tk {
 
 // Final pass: g[b][l] = sum over passes and workgroups of the partials, in a
-// fixed order (compensated).
-__global__ void __launch_bounds__(256) reduce_partials_kernel(ReduceParams p)
+// fixed order (compensated).  A block of 1024 threads takes 8 columns of one
+// vector: 128 slots per column, each with four independent compensated
+// chains (partials w, w + 128, w + 256, w + 384 of each stride of 512), so a
+// per-vector partial count of a few thousand costs a few dependent load
+// rounds; the slots then meet in a fixed tree.
+__global__ void __launch_bounds__(1024) reduce_partials_kernel(ReduceParams p)
 {
-    __shared__ double sh_hi[256], sh_lo[256];
-    const int cols = 8;                       // columns per block
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    constexpr int cols = 8, slots = 128;
+    __shared__ double sh_hi[cols * slots], sh_lo[cols * slots];
     const int lane_col = threadIdx.x % cols;
-    const int slot = threadIdx.x / cols;      // 32 slots
+    const int slot = threadIdx.x / cols;
     const int b = blockIdx.y;
     const int l = blockIdx.x * cols + lane_col;
-    // four independent compensated chains per thread (workgroups w, w + 32,
-    // w + 64, w + 96 of each stride of 128) keep four loads in flight; the
-    // order is fixed, so the result stays reproducible
     DD s4[4] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
     if (l < p.n) {
         for (int ps = 0; ps < p.npass; ++ps) {
             const double *src = p.part[ps] + 2 * ((int64_t)b * p.groups[ps]) * p.n;
             const int G = p.groups[ps];
-            for (int w0 = slot; w0 < G; w0 += 128) {
+            for (int w0 = slot; w0 < G; w0 += 4 * slots) {
+                d2 v[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const int w = w0 + 32 * u;
-                    if (w < G) {
-                        const double *q = src + 2 * ((int64_t)w * p.n + l);
-                        double t, e;
-                        two_sum(s4[u].hi, q[0], t, e);
-                        s4[u].hi = t;
-                        s4[u].lo += e + q[1];
-                    }
+                    const int w = w0 + slots * u;
+                    v[u] = w < G ? *reinterpret_cast<const d2 *>(src + 2 * ((int64_t)w * p.n + l)) : d2{0.0, 0.0};
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    double t, e;
+                    two_sum(s4[u].hi, v[u][0], t, e);
+                    s4[u].hi = t;
+                    s4[u].lo += e + v[u][1];
                 }
             }
         }
@@ -51,7 +55,7 @@ __global__ void __launch_bounds__(256) reduce_partials_kernel(ReduceParams p)
     sh_hi[threadIdx.x] = s.hi;
     sh_lo[threadIdx.x] = s.lo;
     __syncthreads();
-    for (int stride = 16; stride >= 1; stride >>= 1) {
+    for (int stride = slots / 2; stride >= 1; stride >>= 1) {
         if (slot < stride) {
             DD a{sh_hi[threadIdx.x], sh_lo[threadIdx.x]};
             DD c{sh_hi[threadIdx.x + stride * cols], sh_lo[threadIdx.x + stride * cols]};
@@ -175,7 +179,7 @@ hipError_t launch_pass(int q, int in_kind, int mode, int hv, int bt, const PairP
 hipError_t launch_reduce(const ReduceParams &rp, int64_t B, hipStream_t st)
 {
     dim3 grid((rp.n + 7) / 8, (unsigned)B);
-    hipLaunchKernelGGL(reduce_partials_kernel, grid, dim3(256), 0, st, rp);
+    hipLaunchKernelGGL(reduce_partials_kernel, grid, dim3(1024), 0, st, rp);
     return hipGetLastError();
 }
 
