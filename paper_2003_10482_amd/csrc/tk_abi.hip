@@ -950,9 +950,12 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
     };
     // (J_b + lambda I)^{-1} (J_b + diag(h_b) for the logistic loss) by
     // Newton-Schulz on the device, X <- 2 X - X A X with the dense MFMA
-    // products: three steps from the previous inverse (J has moved little),
-    // else forty from I / ||A||_F; kept when ||I - A X||_F < 1/4 (one
-    // synchronisation).  ok = 0 leaves it to the host factorisation.
+    // products: four steps from the previous inverse (J has moved little),
+    // else from I / ||A||_F, where ||I - A X_0||_2 <= 1 - lambda / ||A||_F
+    // (J is positive semidefinite) squares at every step: about
+    // log2(||A||_F / lambda) + 4 steps, ||A||_F taken from the last inverse
+    // (at most 45); kept when ||I - A X||_F < 1/4 (one synchronisation).
+    // ok = 0 leaves it to the host factorisation.
     auto refresh_inverse_device = [&](int64_t b, int &ok) -> int {
         ok = 0;
         if (n < 2 || sb.cw_bytes < 2 * (size_t)n * n * sizeof(double)) return TK_OK;
@@ -966,7 +969,11 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
             const bool warm = attempt == 0;
             if (warm && !(pc[b].dev && !pc[b].ident)) continue;   // no previous inverse
             if (!warm) TK_HIP_CHECK(ns_init(J, lb, dg, X, n, st));
-            const int iters = warm ? 3 : 40;
+            int iters = warm ? 4 : 45;
+            if (!warm && pc[b].jnorm > 0) {
+                const double afro = pc[b].jnorm + lb * std::sqrt((double)n);
+                iters = std::min(45, std::max(8, (int)std::ceil(std::log2(afro / lb)) + 5));
+            }
             for (int k = 0; k < iters; ++k) {
                 TK_HIP_CHECK(launch_gemm(J, n, X, n, 1, T, n, n, n, n, 1, st));   // T = A X
                 TK_HIP_CHECK(ns_shift(T, X, lb, dg, n, st));

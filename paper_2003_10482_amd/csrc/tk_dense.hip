@@ -32,13 +32,24 @@ __global__ void __launch_bounds__(256) gemm_f64_mfma(const double *__restrict__ 
     const int64_t ar = row0 + (lane & 15);
     const int64_t bc = col0 + (lane & 15);
     const int kk = lane >> 4;
-    v4d acc = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t k0 = 0; k0 < Kd; k0 += 4) {
-        const int64_t k = k0 + kk;
-        const double a = (ar < M && k < Kd) ? A[ar * lda + k] : 0.0;
-        const double b = (bc < N && k < Kd) ? Bm[k * bsk + bc * bsj] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    // eight k-steps of operands loaded ahead of their MFMAs, two accumulators
+    constexpr int U = 8;
+    v4d acc = {0.0, 0.0, 0.0, 0.0}, acc2 = acc;
+    for (int64_t k0 = 0; k0 < Kd; k0 += 4 * U) {
+        double a[U], b[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = k0 + 4 * u + kk;
+            a[u] = (ar < M && k < Kd) ? A[ar * lda + k] : 0.0;
+            b[u] = (bc < N && k < Kd) ? Bm[k * bsk + bc * bsj] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; u += 2) {
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+            acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u + 1], b[u + 1], acc2, 0, 0, 0);
+        }
     }
+    acc += acc2;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int64_t r = row0 + 4 * j + (lane >> 4);
