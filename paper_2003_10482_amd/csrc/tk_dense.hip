@@ -11,8 +11,9 @@ namespace {
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 // C[i][j] = sum_k A[i*lda + k] * B[k*bsk + j*bsj]  (i < M, j < N, k < Kd), then
-// an optional elementwise power (epi > 1: C = C^epi).  One wave per 16x16 tile
-// of C; the K loop feeds v_mfma_f64_16x16x4f64 four k at a time:
+// an optional elementwise power (epi > 1: C = C^epi).  One workgroup per 16x16
+// tile of C (four waves splitting the k-steps); the K loop feeds
+// v_mfma_f64_16x16x4f64 four k at a time:
 //   A operand: lane holds A[row0 + lane%16][k0 + lane/16]
 //   B operand: lane holds B[k0 + lane/16][col0 + lane%16]
 //   result:    lane holds C[row0 + 4*j + lane/16][col0 + lane%16], j = 0..3
@@ -23,23 +24,24 @@ __global__ void __launch_bounds__(256) gemm_f64_mfma(const double *__restrict__ 
                                                      int64_t ldc, int64_t M, int64_t N, int64_t Kd,
                                                      int epi)
 {
+    // wave w sums the k-steps w, w + 4, ... (K / 16 MFMAs each, eight k-steps
+    // of operands loaded ahead); the four partial tiles meet in LDS in a
+    // fixed order
+    __shared__ double red[4][4][64];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int64_t tile_n = (int64_t)blockIdx.x * 4 + wave;   // 4 waves = 4 column tiles
     const int64_t row0 = (int64_t)blockIdx.y * 16;
-    const int64_t col0 = tile_n * 16;
-    if (col0 >= N) return;
+    const int64_t col0 = (int64_t)blockIdx.x * 16;
     const int64_t ar = row0 + (lane & 15);
     const int64_t bc = col0 + (lane & 15);
     const int kk = lane >> 4;
-    // eight k-steps of operands loaded ahead of their MFMAs, two accumulators
     constexpr int U = 8;
     v4d acc = {0.0, 0.0, 0.0, 0.0}, acc2 = acc;
-    for (int64_t k0 = 0; k0 < Kd; k0 += 4 * U) {
+    for (int64_t kb = 4 * wave; kb < Kd; kb += 16 * U) {
         double a[U], b[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t k = k0 + 4 * u + kk;
+            const int64_t k = kb + 16 * u + kk;   // k-steps wave, wave + 4, wave + 8, ... (4 k each)
             a[u] = (ar < M && k < Kd) ? A[ar * lda + k] : 0.0;
             b[u] = (bc < N && k < Kd) ? Bm[k * bsk + bc * bsj] : 0.0;
         }
@@ -51,11 +53,15 @@ __global__ void __launch_bounds__(256) gemm_f64_mfma(const double *__restrict__ 
     }
     acc += acc2;
 #pragma unroll
+    for (int j = 0; j < 4; ++j) red[wave][j][lane] = acc[j];
+    __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int64_t r = row0 + 4 * j + (lane >> 4);
         const int64_t c = col0 + (lane & 15);
         if (r < M && c < N) {
-            double v = acc[j];
+            double v = (red[0][j][lane] + red[1][j][lane]) + (red[2][j][lane] + red[3][j][lane]);
             if (epi > 1) {
                 double pw = 1.0;
                 for (int e = 0; e < epi; ++e) pw *= v;
@@ -120,7 +126,7 @@ hipError_t launch_gemm(const double *A, int64_t lda, const double *B, int64_t bs
                        double *C, int64_t ldc, int64_t M, int64_t N, int64_t K, int epi,
                        hipStream_t st)
 {
-    dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 15) / 16));
+    dim3 grid((unsigned)((N + 15) / 16), (unsigned)((M + 15) / 16));
     hipLaunchKernelGGL(gemm_f64_mfma, grid, dim3(256), 0, st, A, lda, B, bsk, bsj, C, ldc, M, N, K,
                        epi);
     return hipGetLastError();
