@@ -958,7 +958,7 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
     // ok = 0 leaves it to the host factorisation.
     auto refresh_inverse_device = [&](int64_t b, int &ok) -> int {
         ok = 0;
-        if (n < 2 || sb.cw_bytes < 2 * (size_t)n * n * sizeof(double)) return TK_OK;
+        if (n < 2 || sb.cw_bytes < (2 * (size_t)n * n + kNsResidualDoubles) * sizeof(double)) return TK_OK;
         double *X = sb.P + b * n * n;
         const double *J = sb.Jd + b * n * n;
         double *T = reinterpret_cast<double *>(sb.cw);
@@ -974,15 +974,16 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                 const double afro = pc[b].jnorm + lb * std::sqrt((double)n);
                 iters = std::min(45, std::max(8, (int)std::ceil(std::log2(afro / lb)) + 5));
             }
-            for (int k = 0; k < iters; ++k) {
-                TK_HIP_CHECK(launch_gemm(J, n, X, n, 1, T, n, n, n, n, 1, st));   // T = A X
-                TK_HIP_CHECK(ns_shift(T, X, lb, dg, n, st));
-                TK_HIP_CHECK(launch_gemm(X, n, T, n, 1, XT, n, n, n, n, 1, st));  // XT = X A X
-                TK_HIP_CHECK(ns_update(X, XT, n, st));
+            // the iterates alternate between X and XT; the symmetrised last one lands in X
+            double *xs[2] = {X, XT};
+            int cur = 0;
+            for (int k = 0; k < iters; ++k, cur ^= 1) {
+                TK_HIP_CHECK(launch_gemm_square(J, xs[cur], T, n, kEpiShift, xs[cur], dg, lb, st));   // T = A X
+                TK_HIP_CHECK(launch_gemm_square(xs[cur], T, xs[cur ^ 1], n, kEpiReflect, xs[cur], nullptr, 0.0,
+                                                st));   // 2 X - X A X
             }
-            TK_HIP_CHECK(ns_symmetrize(X, n, st));
-            TK_HIP_CHECK(launch_gemm(J, n, X, n, 1, T, n, n, n, n, 1, st));
-            TK_HIP_CHECK(ns_shift(T, X, lb, dg, n, st));
+            TK_HIP_CHECK(ns_symmetrize(xs[cur], X, n, st));
+            TK_HIP_CHECK(launch_gemm_square(J, X, T, n, kEpiShift, X, dg, lb, st));
             TK_HIP_CHECK(ns_residual(T, J, n, XT, st));
             double out[2];
             TK_HIP_CHECK(hipMemcpyAsync(out, XT, 2 * sizeof(double), hipMemcpyDeviceToHost, st));

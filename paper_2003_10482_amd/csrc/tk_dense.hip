@@ -11,7 +11,9 @@ namespace {
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 // C[i][j] = sum_k A[i*lda + k] * B[k*bsk + j*bsj]  (i < M, j < N, k < Kd), then
-// an optional elementwise power (epi > 1: C = C^epi).  One workgroup per 16x16
+// one epilogue: epi > 1 raises C to the power epi; epi == kEpiShift adds
+// d_i Y[i][j] (d_i = yd[i], or ys without yd); epi == kEpiReflect gives
+// 2 Y[i][j] - C (Y has leading dimension ldc).  One workgroup per 16x16
 // tile of C (four waves splitting the k-steps); the K loop feeds
 // v_mfma_f64_16x16x4f64 four k at a time:
 //   A operand: lane holds A[row0 + lane%16][k0 + lane/16]
@@ -22,7 +24,8 @@ __global__ void __launch_bounds__(256) gemm_f64_mfma(const double *__restrict__ 
                                                      const double *__restrict__ Bm, int64_t bsk,
                                                      int64_t bsj, double *__restrict__ C,
                                                      int64_t ldc, int64_t M, int64_t N, int64_t Kd,
-                                                     int epi)
+                                                     int epi, const double *__restrict__ Y,
+                                                     const double *__restrict__ yd, double ys)
 {
     // wave w sums the k-steps w, w + 4, ... (K / 16 MFMAs each, eight k-steps
     // of operands loaded ahead); the four partial tiles meet in LDS in a
@@ -62,7 +65,11 @@ __global__ void __launch_bounds__(256) gemm_f64_mfma(const double *__restrict__ 
         const int64_t c = col0 + (lane & 15);
         if (r < M && c < N) {
             double v = (red[0][j][lane] + red[1][j][lane]) + (red[2][j][lane] + red[3][j][lane]);
-            if (epi > 1) {
+            if (epi == kEpiShift) {
+                v = __builtin_fma(yd ? yd[r] : ys, Y[r * ldc + c], v);
+            } else if (epi == kEpiReflect) {
+                v = 2.0 * Y[r * ldc + c] - v;
+            } else if (epi > 1) {
                 double pw = 1.0;
                 for (int e = 0; e < epi; ++e) pw *= v;
                 v = pw;
@@ -128,7 +135,16 @@ hipError_t launch_gemm(const double *A, int64_t lda, const double *B, int64_t bs
 {
     dim3 grid((unsigned)((N + 15) / 16), (unsigned)((M + 15) / 16));
     hipLaunchKernelGGL(gemm_f64_mfma, grid, dim3(256), 0, st, A, lda, B, bsk, bsj, C, ldc, M, N, K,
-                       epi);
+                       epi, (const double *)nullptr, (const double *)nullptr, 0.0);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_square(const double *A, const double *B, double *C, int64_t n, int epi, const double *Y,
+                              const double *yd, double ys, hipStream_t st)
+{
+    if ((epi == kEpiShift || epi == kEpiReflect) && (Y == nullptr || Y == C)) return hipErrorInvalidValue;
+    dim3 grid((unsigned)((n + 15) / 16), (unsigned)((n + 15) / 16));
+    hipLaunchKernelGGL(gemm_f64_mfma, grid, dim3(256), 0, st, A, n, B, n, (int64_t)1, C, n, n, n, n, epi, Y, yd, ys);
     return hipGetLastError();
 }
 

@@ -432,29 +432,21 @@ __global__ void __launch_bounds__(256) ns_init_kernel(const double *__restrict__
     for (int64_t k = threadIdx.x; k < (int64_t)n * n; k += 256) X[k] = (k / n == k % n) ? s : 0.0;
 }
 
-__global__ void __launch_bounds__(256) ns_shift_kernel(double *__restrict__ T, const double *__restrict__ X, double lam,
-                                                       const double *__restrict__ diag, int n)
-{
-    const int64_t nn = (int64_t)n * n;
-    for (int64_t k = blockIdx.x * 256 + threadIdx.x; k < nn; k += (int64_t)gridDim.x * 256) {
-        const double d = diag ? diag[k / n] : lam;
-        T[k] = __builtin_fma(d, X[k], T[k]);
-    }
-}
-
-__global__ void __launch_bounds__(256) ns_update_kernel(double *__restrict__ X, const double *__restrict__ XT, int n)
-{
-    const int64_t nn = (int64_t)n * n;
-    for (int64_t k = blockIdx.x * 256 + threadIdx.x; k < nn; k += (int64_t)gridDim.x * 256)
-        X[k] = 2.0 * X[k] - XT[k];
-}
-
-__global__ void __launch_bounds__(256) ns_residual_kernel(const double *__restrict__ T, const double *__restrict__ J,
-                                                          int n, double *__restrict__ out)
+// ||I - T||_F^2 and ||J||_F^2 in two stages, each in a fixed order: 64
+// workgroups each sum a contiguous slice of the n^2 entries into part[2 w],
+// part[2 w + 1]; one workgroup then adds the 64 pairs.
+constexpr int kResGroups = 64;
+static_assert(kNsResidualDoubles == 2 + 2 * kResGroups, "residual scratch size");
+__global__ void __launch_bounds__(256) ns_residual_part_kernel(const double *__restrict__ T,
+                                                               const double *__restrict__ J, int n,
+                                                               double *__restrict__ part)
 {
     __shared__ double sh[256];
+    const int64_t nn = (int64_t)n * n;
+    const int64_t per = (nn + kResGroups - 1) / kResGroups;
+    const int64_t k0 = blockIdx.x * per, k1 = (k0 + per) < nn ? (k0 + per) : nn;
     double r = 0.0, f = 0.0;
-    for (int64_t k = threadIdx.x; k < (int64_t)n * n; k += 256) {
+    for (int64_t k = k0 + threadIdx.x; k < k1; k += 256) {
         const double e = (k / n == k % n ? 1.0 : 0.0) - T[k];
         r = __builtin_fma(e, e, r);
         f = __builtin_fma(J[k], J[k], f);
@@ -462,21 +454,35 @@ __global__ void __launch_bounds__(256) ns_residual_kernel(const double *__restri
     const double rs = block_sum_256(r, sh);
     const double fs = block_sum_256(f, sh);
     if (threadIdx.x == 0) {
-        out[0] = sqrt(rs);
-        out[1] = sqrt(fs);
+        part[2 * blockIdx.x] = rs;
+        part[2 * blockIdx.x + 1] = fs;
     }
 }
 
-__global__ void __launch_bounds__(256) ns_symmetrize_kernel(double *__restrict__ X, int n)
+__global__ void ns_residual_final_kernel(const double *__restrict__ part, double *__restrict__ out)
 {
-    // the thread of entry (i, j), j > i, averages the pair and writes both
+    if (threadIdx.x != 0) return;
+    double r = 0.0, f = 0.0;
+    for (int w = 0; w < kResGroups; ++w) {
+        r += part[2 * w];
+        f += part[2 * w + 1];
+    }
+    out[0] = sqrt(r);
+    out[1] = sqrt(f);
+}
+
+__global__ void __launch_bounds__(256) ns_symmetrize_kernel(const double *__restrict__ X, double *__restrict__ Xs,
+                                                            int n)
+{
+    // the thread of entry (i, j), j >= i, averages the pair and writes both
+    // (in place when Xs == X: no other thread touches the pair)
     const int64_t nn = (int64_t)n * n;
     for (int64_t k = blockIdx.x * 256 + threadIdx.x; k < nn; k += (int64_t)gridDim.x * 256) {
         const int i = (int)(k / n), j = (int)(k % n);
-        if (j <= i) continue;
+        if (j < i) continue;
         const double v = 0.5 * (X[k] + X[(int64_t)j * n + i]);
-        X[k] = v;
-        X[(int64_t)j * n + i] = v;
+        Xs[k] = v;
+        Xs[(int64_t)j * n + i] = v;
     }
 }
 
@@ -624,31 +630,18 @@ hipError_t ns_init(const double *J, double lam, const double *diag, double *X, i
     return hipGetLastError();
 }
 
-hipError_t ns_shift(double *T, const double *X, double lam, const double *diag, int64_t n, hipStream_t st)
-{
-    const unsigned g = (unsigned)std::min<int64_t>(256, (n * n + 255) / 256);
-    hipLaunchKernelGGL(ns_shift_kernel, dim3(g), dim3(256), 0, st, T, X, lam, diag, (int)n);
-    return hipGetLastError();
-}
-
-hipError_t ns_update(double *X, const double *XT, int64_t n, hipStream_t st)
-{
-    const unsigned g = (unsigned)std::min<int64_t>(256, (n * n + 255) / 256);
-    hipLaunchKernelGGL(ns_update_kernel, dim3(g), dim3(256), 0, st, X, XT, (int)n);
-    return hipGetLastError();
-}
-
 hipError_t ns_residual(const double *T, const double *J, int64_t n, double *out, hipStream_t st)
 {
-    hipLaunchKernelGGL(ns_residual_kernel, dim3(1), dim3(256), 0, st, T, J, (int)n, out);
+    // out[0 .. 2) receives the norms; out[2 .. 2 + 2 kResGroups) holds the partial sums
+    hipLaunchKernelGGL(ns_residual_part_kernel, dim3(kResGroups), dim3(256), 0, st, T, J, (int)n, out + 2);
+    hipLaunchKernelGGL(ns_residual_final_kernel, dim3(1), dim3(64), 0, st, out + 2, out);
     return hipGetLastError();
 }
 
-hipError_t ns_symmetrize(double *X, int64_t n, hipStream_t st)
+hipError_t ns_symmetrize(const double *X, double *Xs, int64_t n, hipStream_t st)
 {
-    if (n < 2) return hipSuccess;
     const unsigned g = (unsigned)std::min<int64_t>(256, (n * n + 255) / 256);
-    hipLaunchKernelGGL(ns_symmetrize_kernel, dim3(g), dim3(256), 0, st, X, (int)n);
+    hipLaunchKernelGGL(ns_symmetrize_kernel, dim3(g), dim3(256), 0, st, X, Xs, (int)n);
     return hipGetLastError();
 }
 

@@ -56,16 +56,15 @@ hipError_t probe_stream_read(const void *src, int64_t words, uint64_t *sink, int
 hipError_t vec_symv(const double *A, const double *x, double *z, int64_t B, int64_t n, hipStream_t st);
 
 // Newton-Schulz inverse of A = J + diag(d) (d_i = lam, or diag[i] when diag
-// is given), n x n row-major, with the dense MFMA products:
+// is given), n x n row-major; the products (with the shift A X = J X + diag(d)
+// X and the step 2 X - X (A X) in their epilogues) are launch_gemm_square's:
 //   ns_init:     X = I / ||A||_F (every eigenvalue of A X then lies in (0, 1])
-//   ns_shift:    T += diag(d) X   (T = J X before: T = A X)
-//   ns_update:   X = 2 X - XT     (XT = X T)
-//   ns_residual: out[0] = ||I - T||_F, out[1] = ||J||_F (fixed-order sums)
-//   ns_symmetrize: X = (X + X^T) / 2
+//   ns_residual: out[0] = ||I - T||_F, out[1] = ||J||_F (fixed-order sums;
+//                out holds kNsResidualDoubles: the norms, then partial sums)
+//   ns_symmetrize: Xs = (X + X^T) / 2 (Xs may be X)
 hipError_t ns_init(const double *J, double lam, const double *diag, double *X, int64_t n, hipStream_t st);
-hipError_t ns_shift(double *T, const double *X, double lam, const double *diag, int64_t n, hipStream_t st);
-hipError_t ns_update(double *X, const double *XT, int64_t n, hipStream_t st);
+constexpr int64_t kNsResidualDoubles = 2 + 2 * 64;
 hipError_t ns_residual(const double *T, const double *J, int64_t n, double *out, hipStream_t st);
-hipError_t ns_symmetrize(double *X, int64_t n, hipStream_t st);
+hipError_t ns_symmetrize(const double *X, double *Xs, int64_t n, hipStream_t st);
 
 }  // namespace tk
