@@ -268,16 +268,19 @@ __device__ __forceinline__ void acc_unit(float &acc, float c, float z) { acc = _
 // the level q-1 update touches block KB only.  Loads address the row through a
 // uniform pointer plus the lane's constant offset.
 
-// Rows per batch: about 16 loads per batch, 32 for BF16 storage (its
+// Rows loaded per batch: about 16 loads per batch, 32 for BF16 storage (its
 // loads and conversions, not HBM, bound the pass: more rows in flight
-// measured 14 % faster there and slower for FP64).
-template <int NB, int KB, int RBMAX, bool WIDE = false>
+// measured 14 % faster there and slower for FP64).  Rows of the last column
+// block (at most 64 entries, about half of each load left of the diagonal)
+// come 16 at a time, so a batch there still carries several KB: the pass is
+// bound by the bytes each wave has in flight.  The row partials go through
+// LDS RBMAX rows at a time.
+template <int NB, int KB, bool WIDE = false>
 constexpr int batch_rows_kb()
 {
     constexpr int segs = NB - KB;
     constexpr int r0 = (WIDE ? 32 : 16) / segs;
-    constexpr int r1 = r0 >= 8 ? 8 : r0 >= 4 ? 4 : 2;
-    return r1 > RBMAX ? RBMAX : r1;
+    return (segs == 1 && r0 >= 16) ? 16 : r0 >= 8 ? 8 : r0 >= 4 ? 4 : 2;
 }
 
 template <int Q, int NB, typename TIn, int MODE, int HV, int BT, int RBMAX>
@@ -364,7 +367,8 @@ struct Pass {
     template <int KB>
     __device__ __forceinline__ void batch(int &k, int k_hi, int64_t &off)
     {
-        constexpr int RB = batch_rows_kb<NB, KB, RBMAX, sizeof(TIn) == 2>();
+        constexpr int RB0 = batch_rows_kb<NB, KB, sizeof(TIn) == 2>();
+        constexpr int RB = RB0 < RBMAX ? RB0 : RBMAX;
         constexpr int SEG = NB - KB;
         constexpr int LPR = kWave / RB;
         const int blk_end = (KB + 1) * kWave;
@@ -504,9 +508,11 @@ struct Pass {
     template <int KB>
     __device__ __forceinline__ void batch_fast(int &k, int k_hi, int64_t &off)
     {
-        constexpr int RB = batch_rows_kb<NB, KB, RBMAX, sizeof(TIn) == 2>();
+        constexpr int RB = batch_rows_kb<NB, KB, sizeof(TIn) == 2>();   // rows loaded together
+        constexpr int RBR = RB < RBMAX ? RB : RBMAX;                      // rows per pass through buf
+        static_assert(RB % RBR == 0, "row groups");
         constexpr int SEG = NB - KB;
-        constexpr int LPR = kWave / RB;
+        constexpr int LPR = kWave / RBR;
         const int blk_end = (KB + 1) * kWave;
         const int lim = blk_end < k_hi ? blk_end : k_hi;
         const int nrows = (lim - k) < RB ? (lim - k) : RB;
@@ -545,101 +551,107 @@ struct Pass {
             }
             so += (uint32_t)(n - k - 1 - r) * ES;
         }
-        // ---- phase 2: in-unit column sums and row partials.  Rows past the
-        // batch run with zero row coefficients (their row partials are never
-        // read), so the loads above are not tied to per-row branches.  Plain
-        // modes accumulate odd rows into a second set of column sums, halving
-        // the dependent chains.
+        // ---- phase 2: in-unit column sums and row partials, RBR rows at a
+        // time.  Rows past the batch run with zero row coefficients (their row
+        // partials are never read), so the loads above are not tied to per-row
+        // branches.  Plain modes accumulate odd rows into a second set of
+        // column sums, halving the dependent chains.
         constexpr bool SPLIT = MODE != ACC_DD;
-        PT Uo[BT][SPLIT ? SEG : 1], Udo[BT][SPLIT ? SEG : 1];
 #pragma unroll
-        for (int bt = 0; bt < BT; ++bt)
-#pragma unroll
-            for (int j = 0; j < (SPLIT ? SEG : 1); ++j) {
-                Uo[bt][j] = p_zero<PT>();
-                Udo[bt][j] = p_zero<PT>();
-            }
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            const bool live = r < nrows;
-            const int kr = live ? k + r : k;
-            const int d = lane - (lane_lo + r);
-#pragma unroll
-            for (int bt = 0; bt < BT; ++bt) {
-                const V ak_r = alpha_s[bt * n + kr];
-                const V ak = live ? ak_r : V(0);
-                V vk{};
-                if constexpr (HVP) {
-                    const V vk_r = vdir_s[bt * n + kr];
-                    vk = live ? vk_r : V(0);
-                }
-                PT part = p_zero<PT>(), partd = p_zero<PT>();
-#pragma unroll
-                for (int j = 0; j < SEG; ++j) {
-                    const int b = KB + j;
-                    VIn x = val[r][j];
-                    if (j == 0) x = tie_scale(d, x);
-                    PT &u = (SPLIT && (r & 1)) ? Uo[bt][SPLIT ? j : 0] : U[bt][b];
-                    PT &ud = (SPLIT && (r & 1)) ? Udo[bt][SPLIT ? j : 0] : Ud[bt][b];
-                    acc_cv(u, ak, x);
-                    acc_cv(part, a_l[bt][b], x);
-                    if constexpr (HVP) {
-                        acc_cv(ud, vk, x);
-                        acc_cv(partd, v_l[bt][b], x);
-                        if constexpr (ATAN) {
-                            VIn xd = vald[r][j];
-                            if (j == 0) xd = tie_scale(d, xd);
-                            acc_cv(ud, ak, xd);
-                            acc_cv(partd, a_l[bt][b], xd);
-                        }
-                    }
-                }
-                buf[(r * NC + bt) * kWave + lane] = part;
-                if constexpr (HVP) buf[(r * NC + BT + bt) * kWave + lane] = partd;
-            }
-        }
-        if constexpr (SPLIT) {
+        for (int h = 0; h < RB / RBR; ++h) {
+            const int rb0 = h * RBR;
+            if (rb0 >= nrows) break;
+            PT Uo[BT][SPLIT ? SEG : 1], Udo[BT][SPLIT ? SEG : 1];
 #pragma unroll
             for (int bt = 0; bt < BT; ++bt)
 #pragma unroll
-                for (int j = 0; j < SEG; ++j) {
-                    U[bt][KB + j] = p_add(U[bt][KB + j], Uo[bt][j]);
-                    if constexpr (HVP) Ud[bt][KB + j] = p_add(Ud[bt][KB + j], Udo[bt][j]);
+                for (int j = 0; j < (SPLIT ? SEG : 1); ++j) {
+                    Uo[bt][j] = p_zero<PT>();
+                    Udo[bt][j] = p_zero<PT>();
                 }
-        }
-        __builtin_amdgcn_wave_barrier();
-        // ---- transposed reduction: lanes [r LPR, (r+1) LPR) sum row r
-        {
-            const int r = lane / LPR, seg = lane % LPR;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                const PT *src = buf + (r * NC + c) * kWave + seg * RB;
-                PT s = tree_sum<RB, PT>([&](int j) { return src[j]; });
-                s = group_sum<LPR>(s);
-                if (seg == 0) sbatch[r * NC + c] = s;
-            }
-        }
-        __builtin_amdgcn_wave_barrier();
-        // ---- level Q-1: S_{P',k} joins the column sums at index k (block KB),
-        // and S_{P'} += S_k alpha_k
-        {
-            const int r = lane - lane_lo;
-            if (r >= 0 && r < nrows) {
+            for (int rl = 0; rl < RBR; ++rl) {
+                const int r = rb0 + rl;
+                const bool live = r < nrows;
+                const int kr = live ? k + r : k;
+                const int d = lane - (lane_lo + r);
 #pragma unroll
                 for (int bt = 0; bt < BT; ++bt) {
-                    const PT s = sbatch[r * NC + bt];
-                    U[bt][KB] = p_add(U[bt][KB], s);
-                    acc_cv(unitS[bt], a_l[bt][KB], s);
+                    const V ak_r = alpha_s[bt * n + kr];
+                    const V ak = live ? ak_r : V(0);
+                    V vk{};
                     if constexpr (HVP) {
-                        const PT sd = sbatch[r * NC + BT + bt];
-                        Ud[bt][KB] = p_add(Ud[bt][KB], sd);
-                        acc_cv(unitSd[bt], a_l[bt][KB], sd);
-                        acc_cv(unitSd[bt], v_l[bt][KB], s);
+                        const V vk_r = vdir_s[bt * n + kr];
+                        vk = live ? vk_r : V(0);
+                    }
+                    PT part = p_zero<PT>(), partd = p_zero<PT>();
+#pragma unroll
+                    for (int j = 0; j < SEG; ++j) {
+                        const int b = KB + j;
+                        VIn x = val[r][j];
+                        if (j == 0) x = tie_scale(d, x);
+                        PT &u = (SPLIT && (rl & 1)) ? Uo[bt][SPLIT ? j : 0] : U[bt][b];
+                        PT &ud = (SPLIT && (rl & 1)) ? Udo[bt][SPLIT ? j : 0] : Ud[bt][b];
+                        acc_cv(u, ak, x);
+                        acc_cv(part, a_l[bt][b], x);
+                        if constexpr (HVP) {
+                            acc_cv(ud, vk, x);
+                            acc_cv(partd, v_l[bt][b], x);
+                            if constexpr (ATAN) {
+                                VIn xd = vald[r][j];
+                                if (j == 0) xd = tie_scale(d, xd);
+                                acc_cv(ud, ak, xd);
+                                acc_cv(partd, a_l[bt][b], xd);
+                            }
+                        }
+                    }
+                    buf[(rl * NC + bt) * kWave + lane] = part;
+                    if constexpr (HVP) buf[(rl * NC + BT + bt) * kWave + lane] = partd;
+                }
+            }
+            if constexpr (SPLIT) {
+#pragma unroll
+                for (int bt = 0; bt < BT; ++bt)
+#pragma unroll
+                    for (int j = 0; j < SEG; ++j) {
+                        U[bt][KB + j] = p_add(U[bt][KB + j], Uo[bt][j]);
+                        if constexpr (HVP) Ud[bt][KB + j] = p_add(Ud[bt][KB + j], Udo[bt][j]);
+                    }
+            }
+            __builtin_amdgcn_wave_barrier();
+            // ---- transposed reduction: lanes [r LPR, (r+1) LPR) sum row rb0 + r
+            {
+                const int r = lane / LPR, seg = lane % LPR;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const PT *src = buf + (r * NC + c) * kWave + seg * RBR;
+                    PT s = tree_sum<RBR, PT>([&](int j) { return src[j]; });
+                    s = group_sum<LPR>(s);
+                    if (seg == 0) sbatch[r * NC + c] = s;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            // ---- level Q-1: S_{P',k} joins the column sums at index k (block KB),
+            // and S_{P'} += S_k alpha_k
+            {
+                const int r = lane - lane_lo - rb0;
+                if (r >= 0 && r < RBR && rb0 + r < nrows) {
+#pragma unroll
+                    for (int bt = 0; bt < BT; ++bt) {
+                        const PT s = sbatch[r * NC + bt];
+                        U[bt][KB] = p_add(U[bt][KB], s);
+                        acc_cv(unitS[bt], a_l[bt][KB], s);
+                        if constexpr (HVP) {
+                            const PT sd = sbatch[r * NC + BT + bt];
+                            Ud[bt][KB] = p_add(Ud[bt][KB], sd);
+                            acc_cv(unitSd[bt], a_l[bt][KB], sd);
+                            acc_cv(unitSd[bt], v_l[bt][KB], s);
+                        }
                     }
                 }
             }
+            __builtin_amdgcn_wave_barrier();
         }
-        __builtin_amdgcn_wave_barrier();
         off += (int64_t)nrows * (n - k) - (int64_t)(nrows * (nrows - 1) / 2);
         k += nrows;
     }

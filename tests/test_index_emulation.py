@@ -155,14 +155,15 @@ def test_batch_walk_matches_nested_loop_order(n, qp):
 # ---------------------------------------------------------------------------
 # Vector pass (tk_pass.hpp, batch_fast): buffer offsets of the rows of a unit.
 
-def batch_rows_kb(nb, kb, rbmax):
+def batch_rows_kb(nb, kb):
+    """Rows loaded per batch (FP64/FP32 storage): 16 in the last column
+    block, else about 16 loads."""
     segs = nb - kb
     r0 = 16 // segs
-    r1 = 8 if r0 >= 8 else 4 if r0 >= 4 else 2
-    return min(r1, rbmax)
+    return 16 if (segs == 1 and r0 >= 16) else 8 if r0 >= 8 else 4 if r0 >= 4 else 2
 
 
-def pass_row_offsets(n, k0, rr, rbmax, e_base_rel):
+def pass_row_offsets(n, k0, rr, e_base_rel):
     """Byte offsets (entries, ES = 1) the fast row batches of one unit load, as
     batch_fast computes them: so = off - k - e_base + 64 KB per batch, plus
     lane and segment, minus the tail shift of lanes past n, and
@@ -175,7 +176,7 @@ def pass_row_offsets(n, k0, rr, rbmax, e_base_rel):
     off = 0 if k == k0 else n - k0   # packed offset of row k from (k0, k0)
     while k < n:
         kb = k >> 6
-        rb = batch_rows_kb(nb, kb, rbmax)
+        rb = batch_rows_kb(nb, kb)
         blk_end = (kb + 1) * 64
         lim = min(blk_end, n)
         nrows = min(lim - k, rb)
@@ -205,7 +206,7 @@ def test_vector_pass_row_offsets(n):
             if rr == 2 and k0 == 0 and n == 1:
                 continue
             rel = rel_cache.setdefault(k0, unit_rel(n, k0))
-            for row, l, o, live_row in pass_row_offsets(n, k0, rr, 8, -64):
+            for row, l, o, live_row in pass_row_offsets(n, k0, rr, -64):
                 if live_row:
                     assert row < n and np.all(o >= 0), (n, k0, rr, row)
                     m = (l >= row) & (l < n)
