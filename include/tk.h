@@ -225,11 +225,15 @@ typedef struct {
                             contraction, is assembled by tk_hessian (FP64, on the FP64
                             tensor or the polish tensor) and CG runs on the dense system
                             (J + lambda I) p = -grad, preconditioned with an inverse
-                            (J' + lambda' I)^{-1} factored on the host from an earlier
-                            Hessian; 0: unpreconditioned CG whose products are tk_hvp
-                            passes over the tensor */
-    int precond_refresh; /* refactor the inverse after a Newton step that needed more than
-                            this many CG steps (default 25) */
+                            (J' + lambda' I)^{-1} of an earlier Hessian (Newton-Schulz on
+                            the device, a host Cholesky when that does not settle); 0:
+                            unpreconditioned CG whose products are tk_hvp passes over the
+                            tensor */
+    int precond_refresh; /* remake the inverse after a Newton step that needed more than
+                            this many CG steps (default 25; more than one step while the
+                            last remake was a warm Newton-Schulz update that held), and
+                            whenever lambda has fallen below half the lambda' it was made
+                            at */
     int continuation;    /* B > 1: 1 (default) solves the lambdas one after another from the
                             largest down, each started from the previous solution and keeping
                             its preconditioner; 0: all lambdas in lock step, sharing every

@@ -833,6 +833,12 @@ struct Precond {
     bool have_J = false;
     double moved = 0.0;
     double jnorm = 0.0;   // Frobenius norm of the last J inverted (>= ||J||_2)
+    // the last refresh was a warm Newton-Schulz update (a few steps from the
+    // inverse before it) that held: refreshing is then cheap
+    bool warm_ok = false;
+    // since the held inverse was made: the iterate moved this far, from an
+    // iterate of norm an_inv, and lambda was lam_inv
+    double moved_inv = 0.0, an_inv = 0.0, lam_inv = 0.0;
 };
 
 struct ProblemState {
@@ -958,6 +964,7 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
     // ok = 0 leaves it to the host factorisation.
     auto refresh_inverse_device = [&](int64_t b, int &ok) -> int {
         ok = 0;
+        pc[b].warm_ok = false;
         if (n < 2 || sb.cw_bytes < (2 * (size_t)n * n + kNsResidualDoubles) * sizeof(double)) return TK_OK;
         double *X = sb.P + b * n * n;
         const double *J = sb.Jd + b * n * n;
@@ -965,9 +972,16 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
         double *XT = T + n * n;
         const double *dg = logistic ? sb.hdiag + b * n : nullptr;
         const double lb = ps[b].lam;
+        // ||I - A X_old|| <= (||J - J_old|| + |lambda - lambda_old|) / lambda with
+        // ||J - J_old|| about (m-2) ||J||_F moved / ||alpha|| (J homogeneous of
+        // degree m-2): four steps from X_old square that bound four times, so
+        // they are tried only when it is below 1/2
+        const double rho = pc[b].an_inv > 0 ? ((double)(m - 2) * pc[b].jnorm * pc[b].moved_inv / pc[b].an_inv +
+                                               std::fabs(lb - pc[b].lam_inv)) / lb
+                                            : 1e300;
         for (int attempt = 0; attempt < 2; ++attempt) {
             const bool warm = attempt == 0;
-            if (warm && !(pc[b].dev && !pc[b].ident)) continue;   // no previous inverse
+            if (warm && !(pc[b].dev && !pc[b].ident && rho < 0.5)) continue;   // no usable previous inverse
             if (!warm) TK_HIP_CHECK(ns_init(J, lb, dg, X, n, st));
             int iters = warm ? 4 : 45;
             if (!warm && pc[b].jnorm > 0) {
@@ -988,8 +1002,15 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
             double out[2];
             TK_HIP_CHECK(hipMemcpyAsync(out, XT, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
             TK_HIP_CHECK(spin_sync(st));
+            if (o.verbose)
+                fprintf(stderr, "[tk_solve] inverse %lld: %s Newton-Schulz, %d steps, ||I - A X||_F %.3e\n",
+                        (long long)b, warm ? "warm" : "cold", iters, out[0]);
             if (std::isfinite(out[0]) && out[0] < 0.25) {
                 pc[b].jnorm = out[1];
+                pc[b].warm_ok = warm;
+                pc[b].moved_inv = 0.0;
+                pc[b].an_inv = ps[b].an;
+                pc[b].lam_inv = lb;
                 ok = 1;
                 return TK_OK;
             }
@@ -1047,6 +1068,10 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
         pc_updates[b]++;
         pc[b].dev = true;
         pc[b].ident = zero;
+        pc[b].warm_ok = false;
+        pc[b].moved_inv = 0.0;
+        pc[b].an_inv = zero ? 0.0 : ps[b].an;
+        pc[b].lam_inv = ps[b].lam;
         return TK_OK;
     };
 
@@ -1218,7 +1243,13 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                     // the logistic loss's separable Hessian lambda / (p (1-p)) changes
                     // fast as iterates near the domain's boundary: a stale inverse
                     // then steers CG into the step cap, so it is refreshed every step
-                    if (!pc[b].dev || (pc[b].ident && !zero) || ps[b].last_cg > refresh || logistic)
+                    // after a warm update held, refresh whenever CG needed more than
+                    // one step (along a path J moves little from lambda to lambda);
+                    // an inverse made at a lambda more than twice the current one
+                    // misses the small eigenvalues that now bound CG
+                    const int rlim = pc[b].warm_ok ? 1 : refresh;
+                    const bool lam_fell = pc[b].lam_inv > 2.0 * ps[b].lam;
+                    if (!pc[b].dev || (pc[b].ident && !zero) || ps[b].last_cg > rlim || lam_fell || logistic)
                         if ((rc = refresh_inverse(b, zero))) return rc;
                 }
             }
@@ -1446,6 +1477,7 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                         s.newton++;
                         last_t[b] = t[b];
                         pc[b].moved += t[b] * xnorm[b];
+                        pc[b].moved_inv += t[b] * xnorm[b];
                     } else {
                         t[b] *= 0.5;
                         if (t[b] < 1e-14) {   // no decrease visible: rounding floor of D
