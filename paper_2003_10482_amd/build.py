@@ -23,8 +23,11 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Wno-unused-result", "-munsafe-fp-atomics", "-ffp-contract=off"]
 HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off"]
 # Per-source additions: the batched MFMA pass adds its matrix-core results with
-# vector instructions, so its accumulators stay in VGPRs (no copies through AGPRs).
-EXTRA_FLAGS = {"tk_batch.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+# vector instructions, and the build's sixteen accumulators per wave would
+# otherwise sit in AGPRs beside as many VGPRs (one wave per SIMD): both keep
+# their MFMA accumulators in VGPRs.
+EXTRA_FLAGS = {"tk_batch.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+               "tk_build.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def hipcc() -> str:

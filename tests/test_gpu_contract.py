@@ -51,6 +51,16 @@ def test_build_exact_and_rounded(n, m):
     np.testing.assert_array_equal(to_np(Kb.data.to(torch.float32)).astype(np.float64), P.round_bf16(Kref))
 
 
+@pytest.mark.parametrize("n,m,d", [(250, 2, 37), (256, 2, 5), (70, 4, 37), (17, 6, 19)])
+def test_build_column_tail_and_ragged_features(n, m, d):
+    """Rows up to the full 256 columns with a ragged last 16-column block, and
+    feature counts that end inside a staged chunk: exact on dyadic points."""
+    X = _dyadic_X(n, d, seed=3 * n + m)
+    Kref = T.build_packed(X, m)
+    K64 = tk.build_packed_tensor(to_dev(X), m, dtype="f64")
+    np.testing.assert_array_equal(to_np(K64.data), Kref)
+
+
 @pytest.mark.parametrize("kernel,kparam", [("poly", 2), ("exp", 0.0)])
 def test_build_poly_exp(kernel, kparam):
     n, d, m = 11, 6, 4
