@@ -836,6 +836,10 @@ struct Precond {
     // the last refresh was a warm Newton-Schulz update (a few steps from the
     // inverse before it) that held: refreshing is then cheap
     bool warm_ok = false;
+    // the held inverse came from Newton-Schulz on the device (not the host
+    // factorisation, which takes milliseconds and retries on a J that
+    // rounding left indefinite)
+    bool ns_ok = false;
     // since the held inverse was made: the iterate moved this far, from an
     // iterate of norm an_inv, and lambda was lam_inv
     double moved_inv = 0.0, an_inv = 0.0, lam_inv = 0.0;
@@ -1008,6 +1012,7 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
             if (std::isfinite(out[0]) && out[0] < 0.25) {
                 pc[b].jnorm = out[1];
                 pc[b].warm_ok = warm;
+                pc[b].ns_ok = true;
                 pc[b].moved_inv = 0.0;
                 pc[b].an_inv = ps[b].an;
                 pc[b].lam_inv = lb;
@@ -1069,6 +1074,7 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
         pc[b].dev = true;
         pc[b].ident = zero;
         pc[b].warm_ok = false;
+        pc[b].ns_ok = zero;   // I / lambda: free to remake
         pc[b].moved_inv = 0.0;
         pc[b].an_inv = zero ? 0.0 : ps[b].an;
         pc[b].lam_inv = ps[b].lam;
@@ -1245,10 +1251,13 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                     // then steers CG into the step cap, so it is refreshed every step
                     // after a warm update held, refresh whenever CG needed more than
                     // one step (along a path J moves little from lambda to lambda);
-                    // an inverse made at a lambda more than twice the current one
-                    // misses the small eigenvalues that now bound CG
+                    // an inverse made (on the device) at a lambda more than twice
+                    // the current one misses the small eigenvalues that now bound CG;
+                    // not on a J from reduced storage, whose rounding leaves it
+                    // indefinite at small lambda
                     const int rlim = pc[b].warm_ok ? 1 : refresh;
-                    const bool lam_fell = pc[b].lam_inv > 2.0 * ps[b].lam;
+                    const bool j_exact = dt == TK_F64 || o.polish_K;
+                    const bool lam_fell = j_exact && pc[b].ns_ok && pc[b].lam_inv > 2.0 * ps[b].lam;
                     if (!pc[b].dev || (pc[b].ident && !zero) || ps[b].last_cg > rlim || lam_fell || logistic)
                         if ((rc = refresh_inverse(b, zero))) return rc;
                 }
