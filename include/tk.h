@@ -231,7 +231,8 @@ typedef struct {
                             tensor */
     int precond_refresh; /* remake the inverse after a Newton step that needed more than
                             this many CG steps (default 25; more than one step while the
-                            last remake was a warm Newton-Schulz update that held), and
+                            last remake was a warm Newton-Schulz update that held), and,
+                            for a Hessian from an FP64 tensor inverted on the device,
                             whenever lambda has fallen below half the lambda' it was made
                             at */
     int continuation;    /* B > 1: 1 (default) solves the lambdas one after another from the
