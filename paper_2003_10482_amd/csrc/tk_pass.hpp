@@ -270,17 +270,18 @@ __device__ __forceinline__ void acc_unit(float &acc, float c, float z) { acc = _
 
 // Rows loaded per batch: about 16 loads per batch, 32 for BF16 storage (its
 // loads and conversions, not HBM, bound the pass: more rows in flight
-// measured 14 % faster there and slower for FP64).  Rows of the last column
-// block (at most 64 entries, about half of each load left of the diagonal)
-// come 16 at a time, so a batch there still carries several KB: the pass is
-// bound by the bytes each wave has in flight.  The row partials go through
-// LDS RBMAX rows at a time.
-template <int NB, int KB, bool WIDE = false>
+// measured 14 % faster there and slower for FP64).  With units of two
+// leading indices (order 4: triangles of up to n rows) the rows of the last
+// column block (at most 64 entries, about half of each load left of the
+// diagonal) come 16 at a time (2-4 % faster passes at n = 256); the shorter
+// units of higher orders keep 8 (16 measured 8-12 % slower at order 6).
+// The row partials go through LDS RBMAX rows at a time.
+template <int NB, int KB, bool WIDE = false, bool LONG = false>
 constexpr int batch_rows_kb()
 {
     constexpr int segs = NB - KB;
     constexpr int r0 = (WIDE ? 32 : 16) / segs;
-    return (segs == 1 && r0 >= 16) ? 16 : r0 >= 8 ? 8 : r0 >= 4 ? 4 : 2;
+    return (LONG && segs == 1 && r0 >= 16) ? 16 : r0 >= 8 ? 8 : r0 >= 4 ? 4 : 2;
 }
 
 template <int Q, int NB, typename TIn, int MODE, int HV, int BT, int RBMAX>
@@ -367,7 +368,7 @@ struct Pass {
     template <int KB>
     __device__ __forceinline__ void batch(int &k, int k_hi, int64_t &off)
     {
-        constexpr int RB0 = batch_rows_kb<NB, KB, sizeof(TIn) == 2>();
+        constexpr int RB0 = batch_rows_kb<NB, KB, sizeof(TIn) == 2, Q == 4>();
         constexpr int RB = RB0 < RBMAX ? RB0 : RBMAX;
         constexpr int SEG = NB - KB;
         constexpr int LPR = kWave / RB;
@@ -508,7 +509,7 @@ struct Pass {
     template <int KB>
     __device__ __forceinline__ void batch_fast(int &k, int k_hi, int64_t &off)
     {
-        constexpr int RB = batch_rows_kb<NB, KB, sizeof(TIn) == 2>();   // rows loaded together
+        constexpr int RB = batch_rows_kb<NB, KB, sizeof(TIn) == 2, Q == 4>();   // rows loaded together
         constexpr int RBR = RB < RBMAX ? RB : RBMAX;                      // rows per pass through buf
         static_assert(RB % RBR == 0, "row groups");
         constexpr int SEG = NB - KB;

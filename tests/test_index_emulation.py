@@ -155,15 +155,15 @@ def test_batch_walk_matches_nested_loop_order(n, qp):
 # ---------------------------------------------------------------------------
 # Vector pass (tk_pass.hpp, batch_fast): buffer offsets of the rows of a unit.
 
-def batch_rows_kb(nb, kb):
-    """Rows loaded per batch (FP64/FP32 storage): 16 in the last column
-    block, else about 16 loads."""
+def batch_rows_kb(nb, kb, long_units):
+    """Rows loaded per batch (FP64/FP32 storage): about 16 loads; 16 rows in
+    the last column block for order-4 units (long_units)."""
     segs = nb - kb
     r0 = 16 // segs
-    return 16 if (segs == 1 and r0 >= 16) else 8 if r0 >= 8 else 4 if r0 >= 4 else 2
+    return 16 if (long_units and segs == 1 and r0 >= 16) else 8 if r0 >= 8 else 4 if r0 >= 4 else 2
 
 
-def pass_row_offsets(n, k0, rr, e_base_rel):
+def pass_row_offsets(n, k0, rr, e_base_rel, long_units):
     """Byte offsets (entries, ES = 1) the fast row batches of one unit load, as
     batch_fast computes them: so = off - k - e_base + 64 KB per batch, plus
     lane and segment, minus the tail shift of lanes past n, and
@@ -176,7 +176,7 @@ def pass_row_offsets(n, k0, rr, e_base_rel):
     off = 0 if k == k0 else n - k0   # packed offset of row k from (k0, k0)
     while k < n:
         kb = k >> 6
-        rb = batch_rows_kb(nb, kb)
+        rb = batch_rows_kb(nb, kb, long_units)
         blk_end = (kb + 1) * 64
         lim = min(blk_end, n)
         nrows = min(lim - k, rb)
@@ -192,8 +192,9 @@ def pass_row_offsets(n, k0, rr, e_base_rel):
         k += nrows
 
 
+@pytest.mark.parametrize("long_units", [True, False])
 @pytest.mark.parametrize("n", NS)
-def test_vector_pass_row_offsets(n):
+def test_vector_pass_row_offsets(n, long_units):
     """Live lanes (l >= row, l < n, rows of the batch) read entry (row, l);
     every lane of a row of the batch stays at or above the descriptor base,
     which lies 64 entries before the wave's first entry (here: this unit's).
@@ -206,7 +207,7 @@ def test_vector_pass_row_offsets(n):
             if rr == 2 and k0 == 0 and n == 1:
                 continue
             rel = rel_cache.setdefault(k0, unit_rel(n, k0))
-            for row, l, o, live_row in pass_row_offsets(n, k0, rr, -64):
+            for row, l, o, live_row in pass_row_offsets(n, k0, rr, -64, long_units):
                 if live_row:
                     assert row < n and np.all(o >= 0), (n, k0, rr, row)
                     m = (l >= row) & (l < n)
