@@ -338,16 +338,26 @@ __global__ void __launch_bounds__(1024) cg_dense_kernel(const double *__restrict
         __syncthreads();   // sv and part free
         if (q == 0) sv[i] = in ? v : 0.0;
         __syncthreads();
-        double s0 = 0.0, s1 = 0.0;
+        // eight loads in flight per thread, four chains, fixed order
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
         if (in) {
             int j = j0;
-            for (; j + 1 < j1; j += 2) {
-                s0 = __builtin_fma(M[(int64_t)j * n + i], sv[j], s0);
-                s1 = __builtin_fma(M[(int64_t)(j + 1) * n + i], sv[j + 1], s1);
+            for (; j + 8 <= j1; j += 8) {
+                double m[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) m[u] = M[(int64_t)(j + u) * n + i];
+                s0 = __builtin_fma(m[0], sv[j], s0);
+                s1 = __builtin_fma(m[1], sv[j + 1], s1);
+                s2 = __builtin_fma(m[2], sv[j + 2], s2);
+                s3 = __builtin_fma(m[3], sv[j + 3], s3);
+                s0 = __builtin_fma(m[4], sv[j + 4], s0);
+                s1 = __builtin_fma(m[5], sv[j + 5], s1);
+                s2 = __builtin_fma(m[6], sv[j + 6], s2);
+                s3 = __builtin_fma(m[7], sv[j + 7], s3);
             }
-            if (j < j1) s0 = __builtin_fma(M[(int64_t)j * n + i], sv[j], s0);
+            for (; j < j1; ++j) s0 = __builtin_fma(M[(int64_t)j * n + i], sv[j], s0);
         }
-        part[q][i] = s0 + s1;
+        part[q][i] = (s0 + s1) + (s2 + s3);
         __syncthreads();
         return (part[0][i] + part[1][i]) + (part[2][i] + part[3][i]);
     };
