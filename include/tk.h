@@ -119,8 +119,8 @@ int tk_contract_workspace(int64_t n, int m, int64_t B, int dtype, size_t *h_byte
  * on the FP64 matrix cores, 16 vectors per tile, two tiles per workgroup:
  * each entry is staged once for its row tile and once for its column tile
  * per workgroup, and the workgroups of one range of K share an XCD's L2, so
- * HBM traffic is about three reads of K per launch (measured at n = 256 for
- * B = 64), independent of B only per pair of tiles.  alpha and g
+ * HBM traffic is about three reads of K per launch of 64 vectors (measured
+ * at n = 256), growing with the number of workgroup tiles.  alpha and g
  * are FP64 [B*n].  `acc` selects the accumulation (tk_acc).  The reduction
  * order is fixed for a launch shape (see the reproducibility convention).
  * Errors: TK_EINVAL, TK_ENOMEM (work_bytes too small), TK_EUNSUPPORTED, TK_EHIP.
