@@ -233,6 +233,9 @@ __device__ __forceinline__ void acc_cv(PT &acc, CT c, VT v) { acc_fma(acc, c, v)
 // the last two indices) every coefficient of the entry is halved, exactly.
 __device__ __forceinline__ double tie_scale(int d, double x) { return d < 0 ? 0.0 : (d == 0 ? 0.5 * x : x); }
 __device__ __forceinline__ float tie_scale(int d, float x) { return d < 0 ? 0.0f : (d == 0 ? 0.5f * x : x); }
+// The same with the tie weight w (1/2, or 1/(r+1) on a unit's first row).
+__device__ __forceinline__ double tie_scale_w(int d, double x, double w) { return d < 0 ? 0.0 : (d == 0 ? w * x : x); }
+__device__ __forceinline__ float tie_scale_w(int d, float x, float w) { return d < 0 ? 0.0f : (d == 0 ? w * x : x); }
 __device__ __forceinline__ DD tie_scale(int d, DD x)
 {
     const double f = d < 0 ? 0.0 : (d == 0 ? 0.5 : 1.0);
@@ -303,6 +306,14 @@ struct Pass {
     // unit constants (uniform)
     CT ak0_rr[BT], vk0_rr[BT], cu_tie0[BT], ck_tie0[BT], cud_tie0[BT], vk_tie0[BT];
     CT inv_rr;
+    // plain modes take a unit's first row (run rr > 1) through batch_fast:
+    // row factor inv_rr on alpha_k and tie weight tie0 = 1 / (rr + 1) there,
+    // against 1 and 1/2 on every other row (one batch less per unit: -10 %
+    // for the directional derivatives of FP32 storage and of order 6, -1 to
+    // -4 % elsewhere; the contraction of FP32 storage measured 4 % slower
+    // that way and keeps the general path, as the compensated mode does)
+    static constexpr bool FOLD = MODE != ACC_DD && !(MODE == ACC_PLAIN32 && !HVP && sizeof(TIn) == 4);
+    V tie0;
     int k0, rr;
     // pointers
     const TIn *A;
@@ -362,6 +373,7 @@ struct Pass {
             }
         }
         inv_rr = Coef<MODE>::div(Coef<MODE>::make(1.0), rr);
+        if constexpr (FOLD) tie0 = Coef<MODE>::div(Coef<MODE>::make(1.0), rr + 1);
     }
 
     // Rows [k, k + nrows) with k >> 6 == KB; `off` is the packed offset of row k.
@@ -576,21 +588,33 @@ struct Pass {
                 const bool live = r < nrows;
                 const int kr = live ? k + r : k;
                 const int d = lane - (lane_lo + r);
+                // a unit's first row with a repeated last index (plain modes)
+                V fr = V(1), tw = V(0.5);
+                if constexpr (FOLD) {
+                    const bool first = live && rr > 1 && kr == k0;
+                    fr = first ? inv_rr : V(1);
+                    tw = first ? tie0 : V(0.5);
+                }
 #pragma unroll
                 for (int bt = 0; bt < BT; ++bt) {
                     const V ak_r = alpha_s[bt * n + kr];
-                    const V ak = live ? ak_r : V(0);
+                    V ak = live ? ak_r : V(0);
+                    if constexpr (FOLD) ak = ak * fr;
                     V vk{};
                     if constexpr (HVP) {
                         const V vk_r = vdir_s[bt * n + kr];
                         vk = live ? vk_r : V(0);
+                        if constexpr (FOLD) vk = vk * fr;
                     }
                     PT part = p_zero<PT>(), partd = p_zero<PT>();
 #pragma unroll
                     for (int j = 0; j < SEG; ++j) {
                         const int b = KB + j;
                         VIn x = val[r][j];
-                        if (j == 0) x = tie_scale(d, x);
+                        if (j == 0) {
+                            if constexpr (FOLD) x = tie_scale_w(d, x, tw);
+                            else x = tie_scale(d, x);
+                        }
                         PT &u = (SPLIT && (rl & 1)) ? Uo[bt][SPLIT ? j : 0] : U[bt][b];
                         PT &ud = (SPLIT && (rl & 1)) ? Udo[bt][SPLIT ? j : 0] : Ud[bt][b];
                         acc_cv(u, ak, x);
@@ -600,7 +624,10 @@ struct Pass {
                             acc_cv(partd, v_l[bt][b], x);
                             if constexpr (ATAN) {
                                 VIn xd = vald[r][j];
-                                if (j == 0) xd = tie_scale(d, xd);
+                                if (j == 0) {
+                                    if constexpr (FOLD) xd = tie_scale_w(d, xd, tw);
+                                    else xd = tie_scale(d, xd);
+                                }
                                 acc_cv(ud, ak, xd);
                                 acc_cv(partd, a_l[bt][b], xd);
                             }
@@ -637,13 +664,16 @@ struct Pass {
             {
                 const int r = lane - lane_lo - rb0;
                 if (r >= 0 && r < RBR && rb0 + r < nrows) {
+                    const bool first = FOLD && rr > 1 && k + rb0 + r == k0;
 #pragma unroll
                     for (int bt = 0; bt < BT; ++bt) {
-                        const PT s = sbatch[r * NC + bt];
+                        PT s = sbatch[r * NC + bt];
+                        if constexpr (FOLD) s = first ? s * inv_rr : s;
                         U[bt][KB] = p_add(U[bt][KB], s);
                         acc_cv(unitS[bt], a_l[bt][KB], s);
                         if constexpr (HVP) {
-                            const PT sd = sbatch[r * NC + BT + bt];
+                            PT sd = sbatch[r * NC + BT + bt];
+                            if constexpr (FOLD) sd = first ? sd * inv_rr : sd;
                             Ud[bt][KB] = p_add(Ud[bt][KB], sd);
                             acc_cv(unitSd[bt], a_l[bt][KB], sd);
                             acc_cv(unitSd[bt], v_l[bt][KB], s);
@@ -661,8 +691,9 @@ struct Pass {
     {
         int k = k_lo;
         // the first row of a unit repeats the prefix's last index (run rr):
-        // general coefficients, one row
-        if (rr > 1 && k == k0 && k < k_hi) {
+        // in the compensated mode general coefficients, one row (the plain
+        // modes fold its two weights into batch_fast)
+        if (!FOLD && rr > 1 && k == k0 && k < k_hi) {
             const int kb = k >> 6;
             if (kb == 0) batch<0>(k, k + 1, off);
             else if constexpr (NB > 1) {

@@ -172,7 +172,9 @@ def pass_row_offsets(n, k0, rr, e_base_rel, long_units):
     e_base_rel.  Yields (row, l, offset, live) arrays per batch."""
     nb = (n + 63) // 64
     lane = np.arange(64)
-    k = k0 + 1 if rr > 1 else k0   # the first row of a run goes through the general path
+    # compensated mode: the first row of a run (rr > 1) goes through the
+    # general path; the plain modes start the fast batches at k0 (as rr = 1)
+    k = k0 + 1 if rr > 1 else k0
     off = 0 if k == k0 else n - k0   # packed offset of row k from (k0, k0)
     while k < n:
         kb = k >> 6
