@@ -986,7 +986,7 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
         for (int attempt = 0; attempt < 2; ++attempt) {
             const bool warm = attempt == 0;
             if (warm && !(pc[b].dev && !pc[b].ident && rho < 0.5)) continue;   // no usable previous inverse
-            if (!warm) TK_HIP_CHECK(ns_init(J, lb, dg, X, n, st));
+            if (!warm) TK_HIP_CHECK(ns_init(J, lb, dg, X, n, XT, st));   // XT: scratch until the first step
             int iters = warm ? 4 : 45;
             if (!warm && pc[b].jnorm > 0) {
                 const double afro = pc[b].jnorm + lb * std::sqrt((double)n);

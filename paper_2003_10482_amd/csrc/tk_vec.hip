@@ -427,19 +427,38 @@ __device__ double block_sum_256(double v, double *sh)
     return r;
 }
 
-__global__ void __launch_bounds__(256) ns_init_kernel(const double *__restrict__ J, double lam,
-                                                      const double *__restrict__ diag, double *__restrict__ X, int n)
+// X = I / ||A||_F in two stages: kInitGroups workgroups each sum the squares
+// of a contiguous slice of A = J + diag(d) into part[w]; every thread of the
+// fill then adds the partial sums in the same fixed order.
+constexpr int kInitGroups = 64;
+__global__ void __launch_bounds__(256) ns_init_part_kernel(const double *__restrict__ J, double lam,
+                                                           const double *__restrict__ diag, int n,
+                                                           double *__restrict__ part)
 {
     __shared__ double sh[256];
+    const int64_t nn = (int64_t)n * n;
+    const int64_t per = (nn + kInitGroups - 1) / kInitGroups;
+    const int64_t k0 = blockIdx.x * per, k1 = (k0 + per) < nn ? (k0 + per) : nn;
     double f = 0.0;
-    for (int64_t k = threadIdx.x; k < (int64_t)n * n; k += 256) {
+    for (int64_t k = k0 + threadIdx.x; k < k1; k += 256) {
         const int i = (int)(k / n), j = (int)(k % n);
         const double a = J[k] + (i == j ? (diag ? diag[i] : lam) : 0.0);
         f = __builtin_fma(a, a, f);
     }
-    const double fro = sqrt(block_sum_256(f, sh));
+    const double fs = block_sum_256(f, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = fs;
+}
+
+__global__ void __launch_bounds__(256) ns_init_fill_kernel(const double *__restrict__ part, int n,
+                                                           double *__restrict__ X)
+{
+    double f = 0.0;
+    for (int w = 0; w < kInitGroups; ++w) f += part[w];
+    const double fro = sqrt(f);
     const double s = fro > 0.0 ? 1.0 / fro : 0.0;
-    for (int64_t k = threadIdx.x; k < (int64_t)n * n; k += 256) X[k] = (k / n == k % n) ? s : 0.0;
+    const int64_t nn = (int64_t)n * n;
+    for (int64_t k = blockIdx.x * 256 + threadIdx.x; k < nn; k += (int64_t)gridDim.x * 256)
+        X[k] = (k / n == k % n) ? s : 0.0;
 }
 
 // ||I - T||_F^2 and ||J||_F^2 in two stages, each in a fixed order: 64
@@ -447,6 +466,7 @@ __global__ void __launch_bounds__(256) ns_init_kernel(const double *__restrict__
 // part[2 w + 1]; one workgroup then adds the 64 pairs.
 constexpr int kResGroups = 64;
 static_assert(kNsResidualDoubles == 2 + 2 * kResGroups, "residual scratch size");
+static_assert(kNsResidualDoubles >= kInitGroups, "initial-norm scratch size");
 __global__ void __launch_bounds__(256) ns_residual_part_kernel(const double *__restrict__ T,
                                                                const double *__restrict__ J, int n,
                                                                double *__restrict__ part)
@@ -634,9 +654,12 @@ hipError_t vec_poly3(const double *g, const double *a, const double *c, const do
     return hipGetLastError();
 }
 
-hipError_t ns_init(const double *J, double lam, const double *diag, double *X, int64_t n, hipStream_t st)
+hipError_t ns_init(const double *J, double lam, const double *diag, double *X, int64_t n, double *part,
+                   hipStream_t st)
 {
-    hipLaunchKernelGGL(ns_init_kernel, dim3(1), dim3(256), 0, st, J, lam, diag, X, (int)n);
+    hipLaunchKernelGGL(ns_init_part_kernel, dim3(kInitGroups), dim3(256), 0, st, J, lam, diag, (int)n, part);
+    const unsigned g = (unsigned)std::min<int64_t>(256, (n * n + 255) / 256);
+    hipLaunchKernelGGL(ns_init_fill_kernel, dim3(g), dim3(256), 0, st, part, (int)n, X);
     return hipGetLastError();
 }
 

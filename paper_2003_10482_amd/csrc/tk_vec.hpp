@@ -58,11 +58,13 @@ hipError_t vec_symv(const double *A, const double *x, double *z, int64_t B, int6
 // Newton-Schulz inverse of A = J + diag(d) (d_i = lam, or diag[i] when diag
 // is given), n x n row-major; the products (with the shift A X = J X + diag(d)
 // X and the step 2 X - X (A X) in their epilogues) are launch_gemm_square's:
-//   ns_init:     X = I / ||A||_F (every eigenvalue of A X then lies in (0, 1])
+//   ns_init:     X = I / ||A||_F (every eigenvalue of A X then lies in (0, 1]);
+//                part holds kNsResidualDoubles doubles of scratch
 //   ns_residual: out[0] = ||I - T||_F, out[1] = ||J||_F (fixed-order sums;
 //                out holds kNsResidualDoubles: the norms, then partial sums)
 //   ns_symmetrize: Xs = (X + X^T) / 2 (Xs may be X)
-hipError_t ns_init(const double *J, double lam, const double *diag, double *X, int64_t n, hipStream_t st);
+hipError_t ns_init(const double *J, double lam, const double *diag, double *X, int64_t n, double *part,
+                   hipStream_t st);
 constexpr int64_t kNsResidualDoubles = 2 + 2 * 64;
 hipError_t ns_residual(const double *T, const double *J, int64_t n, double *out, hipStream_t st);
 hipError_t ns_symmetrize(const double *X, double *Xs, int64_t n, hipStream_t st);
