@@ -1148,8 +1148,11 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                     // plain FP64 gradients still steer Newton well down to
                     // ||grad|| ~ 1e-7 ||y|| (switching there rather than at 1e-5
                     // saved a compensated step at n = 256 and left the lambda
-                    // path unchanged); convergence is only decided on compensated ones
-                    if (ps[b].gn <= 1e-7 * ynorm || ps[b].gn <= tol * ps[b].lam * ps[b].an || flat[b] >= 2) sw = true;
+                    // path unchanged); convergence is only decided on compensated
+                    // ones.  Reduced storage keeps 1e-5: its solves meet the
+                    // storage floor, and a later switch measured 35 % slower there.
+                    const double sw_at = dt == TK_F64 ? 1e-7 : 1e-5;
+                    if (ps[b].gn <= sw_at * ynorm || ps[b].gn <= tol * ps[b].lam * ps[b].an || flat[b] >= 2) sw = true;
                 }
                 if (sw) {
                     accurate = true;
@@ -1493,7 +1496,11 @@ int solve_batch(const void *K, int dtype, int64_t n, int m, const double *y, con
                         pc[b].moved_inv += t[b] * xnorm[b];
                     } else {
                         t[b] *= 0.5;
-                        if (t[b] < 1e-14) {   // no decrease visible: rounding floor of D
+                        // reduced storage: D comes from FP32-accumulated passes, so a
+                        // first-order decrease below about 1e-6 |D| is noise: that is
+                        // the floor too (halving on to 1e-14 cost ~40 passes per lambda)
+                        const bool noise = reduced && t[b] * std::fabs(slope[b]) < 1e-6 * (std::fabs(ps[b].D) + 1.0);
+                        if (t[b] < 1e-14 || noise) {   // no decrease visible: rounding floor of D
                             ls[b] = false;
                             if (accurate) {
                                 ps[b].done = true;
