@@ -260,7 +260,9 @@ typedef enum {
     TK_STOP_SUPPORT = 1, /* the stable-support rule (opts.support_stop) */
     TK_STOP_FLOOR = 2    /* reduced-precision storage without a polish tensor: the gradient
                             stopped falling at the noise floor of the storage rounding (no
-                            halving in 3 Newton steps, or growth 1000x past its best); the
+                            halving in 3 Newton steps, growth 1000x past its best, or a
+                            line search whose predicted decrease is below the FP32 noise
+                            of the objective, 1e-6 |D|); the
                             iterate of smallest gradient is returned and grad_norm is its
                             reduced-precision gradient.  By lambda-strong convexity the
                             error of alpha is at most ||grad D(alpha)|| / lambda with the
